@@ -1,0 +1,282 @@
+"""FP64 CPU oracle of the PSD-cone projection by composite polynomial filtering.
+
+ORACLE — test infrastructure only. It shares no code with the HIP library and
+is imported only by tests/, the smoke check and the benchmark's CPU-baseline
+leg. Everything here is plain FP64 numpy; a matrix product (``@``) and a small
+symmetric eigensolver (``numpy.linalg.eigh`` on the Lanczos tridiagonal) are the
+only library primitives used as steps.
+
+Functions and the passages they follow:
+
+* ``project_exact``      — the projection problem, eq. (1), solved by the
+                           closed form of eq. (3) with a Jacobi eigensolver.
+* ``lanczos_bound``      — Theorem 2 (residual-norm bound on ||A||_2) with the
+                           largest Ritz pair of a 20-step Lanczos run on X^2
+                           (Section 3.4, "Digit loss during matrix rescaling";
+                           Algorithm 2, first two steps).
+* ``project_poly``       — Algorithm 2 (run-time projection): rescale by the
+                           bound, apply the T filter stages, return
+                           lambda * X0 (I + X_T) / 2.
+* ``g_scalar``           — the scalar function the matrix filter applies to
+                           each scaled eigenvalue, eq. (5)/(11):
+                           x (1 + p(x)) / 2.
+* ``efloat``             — eq. (12), the maximum error over all float32 values
+                           in [-1, 1].
+
+Readings of the paper taken here (each also listed in the design notes):
+
+* The input is symmetric and only its upper triangle is read.
+* The Lanczos start vector is a fixed pseudo-random vector from the SplitMix64
+  counter generator (seed 0), normalised; full reorthogonalisation by two
+  passes of classical Gram-Schmidt; stop early when beta <= 1e-13 max|alpha|.
+* Guard (not in the paper): the bound must be at least the largest column norm
+  (a valid lower bound on ||X||_2), else the Frobenius norm is used; the bound
+  is also capped by the Frobenius norm, itself an upper bound on ||X||_2.
+* Stage rescale placement: see ``oracle.tables``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import tables
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+LANCZOS_STEPS = 20
+LANCZOS_SEED = 0
+BREAKDOWN_RTOL = 1e-13
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_jacobi_eig.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double]
+        lib.oracle_jacobi_eig.restype = ctypes.c_int
+        lib.oracle_project_jacobi.argtypes = [ctypes.c_int, dp, dp, dp]
+        lib.oracle_project_jacobi.restype = ctypes.c_int
+        lib.oracle_efloat.argtypes = [ctypes.c_int, dp, dp]
+        lib.oracle_efloat.restype = ctypes.c_double
+        _LIB = lib
+    return _LIB
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------------------
+# Input handling
+# ---------------------------------------------------------------------------
+def sym_from_upper(X) -> np.ndarray:
+    """FP64 symmetric matrix built from the upper triangle of X (uplo = 'U')."""
+    X = np.asarray(X, dtype=np.float64)
+    U = np.triu(X)
+    return U + np.triu(X, 1).T
+
+
+# ---------------------------------------------------------------------------
+# Lanczos start vector: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), used as
+# a counter-based generator: z_i = mix(seed + (i + 1) * golden_gamma).
+# ---------------------------------------------------------------------------
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(counter: np.ndarray, seed: int = 0) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def start_vector(n: int, seed: int = LANCZOS_SEED) -> np.ndarray:
+    """Entries uniform in [-1, 1): 2 * (z >> 11) * 2^-53 - 1 (not normalised)."""
+    z = splitmix64(np.arange(n, dtype=np.uint64), seed)
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return 2.0 * u - 1.0
+
+
+# ---------------------------------------------------------------------------
+# Spectral bound (Theorem 2 + Lanczos on X^2)
+# ---------------------------------------------------------------------------
+def lanczos_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZOS_SEED):
+    """Largest Ritz pair (sigma, q) of ``steps`` Lanczos steps on A = X^2
+    (A applied as X (X v), never formed), then the bound
+    lambda = sqrt(sigma + ||A q - sigma q||_2) of Theorem 2.
+
+    Returns dict(lam, sigma, r, k) with k the number of Lanczos steps taken."""
+    n = Xs.shape[0]
+    v = start_vector(n, seed)
+    v = v / np.linalg.norm(v)
+    V = np.zeros((n, steps), dtype=np.float64)
+    V[:, 0] = v
+    alpha, beta = [], []
+    k = 0
+    for j in range(steps):
+        w = Xs @ (Xs @ V[:, j])
+        h = V[:, : j + 1].T @ w          # first Gram-Schmidt pass
+        alpha.append(h[j])                # alpha_j = v_j^T A v_j
+        w = w - V[:, : j + 1] @ h
+        h2 = V[:, : j + 1].T @ w         # second pass (reorthogonalisation)
+        w = w - V[:, : j + 1] @ h2
+        b = float(np.linalg.norm(w))
+        k = j + 1
+        amax = max(abs(a) for a in alpha)
+        if j == steps - 1 or not (b > BREAKDOWN_RTOL * amax):
+            break
+        beta.append(b)
+        V[:, j + 1] = w / b
+    Tm = np.diag(np.array(alpha[:k])) + np.diag(np.array(beta[: k - 1]), 1) \
+        + np.diag(np.array(beta[: k - 1]), -1)
+    theta, S = np.linalg.eigh(Tm)
+    sigma = float(theta[-1])
+    q = V[:, :k] @ S[:, -1]
+    q = q / np.linalg.norm(q)
+    res = Xs @ (Xs @ q) - sigma * q
+    r = float(np.linalg.norm(res))
+    lam = float(np.sqrt(max(sigma + r, 0.0)))
+    return {"lam": lam, "sigma": sigma, "r": r, "k": k}
+
+
+def spectral_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS):
+    """Lanczos bound with the guard and the Frobenius cap. Returns dict with
+    lam, fro, colmax, fallback (bool) and the Lanczos fields."""
+    fro = float(np.sqrt(np.sum(Xs * Xs)))
+    colmax = float(np.sqrt(np.max(np.sum(Xs * Xs, axis=0)))) if Xs.size else 0.0
+    out = {"fro": fro, "colmax": colmax}
+    if fro == 0.0:
+        out.update(lam=0.0, sigma=0.0, r=0.0, k=0, fallback=False)
+        return out
+    lz = lanczos_bound(Xs, steps)
+    out.update(lz)
+    lam = lz["lam"]
+    fallback = not (lam >= colmax)
+    if fallback:
+        lam = fro
+    out["lam"] = min(lam, fro)
+    out["fallback"] = fallback
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Composite filter (Algorithm 2)
+# ---------------------------------------------------------------------------
+def stage_rows(mode: str) -> np.ndarray:
+    """(a, b, c) per stage with the stage rescale folded in, FP64."""
+    return tables.runtime_table(tables.MODE_TABLE[mode])
+
+
+def composite_scalar(x, rows: np.ndarray):
+    x = np.asarray(x, dtype=np.float64)
+    for a, b, c in rows:
+        x2 = x * x
+        x = x * (a + x2 * (b + x2 * c))
+    return x
+
+
+def g_scalar(x, mode: str = "fp16"):
+    """x (1 + p(x)) / 2 — the approximation of ReLU on the scaled interval."""
+    x = np.asarray(x, dtype=np.float64)
+    return 0.5 * x * (1.0 + composite_scalar(x, stage_rows(mode)))
+
+
+def project_poly(X, mode: str = "fp16", lam: float | None = None,
+                 steps: int = LANCZOS_STEPS):
+    """Algorithm 2 in FP64. ``lam`` overrides the spectral bound (so that the
+    oracle evaluates exactly the function the device evaluated).
+
+    Returns (P, info) with P FP64 n x n symmetric."""
+    Xs = sym_from_upper(X)
+    n = Xs.shape[0]
+    if n == 0:
+        return Xs.copy(), {"lam": 0.0}
+    if not np.all(np.isfinite(Xs)):
+        raise ValueError("non-finite input")
+    if lam is None:
+        info = spectral_bound(Xs, steps)
+        lam = info["lam"]
+    else:
+        info = {"lam": float(lam), "fro": float(np.sqrt(np.sum(Xs * Xs)))}
+    if lam == 0.0:
+        return np.zeros_like(Xs), info
+    X0 = Xs / lam
+    Y = X0
+    for a, b, c in stage_rows(mode):
+        A = Y @ Y
+        B = b * A + c * (A @ A)
+        Y = a * Y + Y @ B
+    P = lam * 0.5 * (X0 + X0 @ Y)
+    P = 0.5 * (P + P.T)
+    return P, info
+
+
+def gemm_count(mode: str) -> int:
+    """3 products per odd quintic stage plus the final X0 X_T."""
+    return 3 * stage_rows(mode).shape[0] + 1
+
+
+# ---------------------------------------------------------------------------
+# Exact projection (eq. (1) via the closed form eq. (3))
+# ---------------------------------------------------------------------------
+def project_exact(X, return_eigs: bool = False):
+    """Q diag(max(lambda, 0)) Q^T with a cyclic Jacobi eigensolver (plain C)."""
+    Xs = np.ascontiguousarray(sym_from_upper(X))
+    n = Xs.shape[0]
+    out = np.zeros_like(Xs)
+    w = np.zeros(max(n, 1))
+    if n:
+        sweeps = _lib().oracle_project_jacobi(n, _dp(Xs), _dp(out), _dp(w))
+        if sweeps < 0:
+            raise RuntimeError("Jacobi did not converge")
+    return (out, w[:n]) if return_eigs else out
+
+
+def jacobi_eig(X):
+    """Eigenvalues and eigenvectors (columns) of a symmetric FP64 matrix."""
+    A = np.ascontiguousarray(sym_from_upper(X)).copy()
+    n = A.shape[0]
+    V = np.zeros_like(A)
+    w = np.zeros(max(n, 1))
+    sweeps = _lib().oracle_jacobi_eig(n, _dp(A), _dp(V), _dp(w), 60, 1e-15)
+    if sweeps < 0:
+        raise RuntimeError("Jacobi did not converge")
+    return w[:n], V
+
+
+def project_exact_eigh(X):
+    """Same closed form with LAPACK's eigh (a library cross-check, any n)."""
+    Xs = sym_from_upper(X)
+    w, Q = np.linalg.eigh(Xs)
+    return (Q * np.maximum(w, 0.0)) @ Q.T
+
+
+def project_spectral(Q: np.ndarray, lam_vals: np.ndarray, fn) -> np.ndarray:
+    """Q diag(fn(lambda)) Q^T for a matrix built from a known spectrum — the
+    spectral-operator identity (eq. (4)/(5)) used as an exact reference."""
+    return (Q * fn(np.asarray(lam_vals, dtype=np.float64))) @ Q.T
+
+
+# ---------------------------------------------------------------------------
+# e_float (eq. (12))
+# ---------------------------------------------------------------------------
+def efloat(table: str, with_rescale: bool = False):
+    """Returns (twice_err, argmax): max over float32 x in [0, 1] of
+    |x p(x) - x|. The literal ReLU error of eq. (12) is half of it."""
+    rows = tables.runtime_table(table) if with_rescale else tables.TABLES[table]
+    abc = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1)
+    arg = ctypes.c_double(0.0)
+    e = _lib().oracle_efloat(rows.shape[0], _dp(abc), ctypes.byref(arg))
+    return float(e), float(arg.value)
