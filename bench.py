@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the PSD-cone projection on one MI355X.
+
+Workload: one dense symmetric n = 10,000 matrix (the paper's headline size),
+GOE spectrum X = (G + G^T) / sqrt(2n), G seeded N(0, 1) (or the rank-500 PSD +
+noise matrix with --input lowrank), FP32 in HBM before the timed region.
+A "step" is one full projection: Lanczos bound, rescale/cast, T filter stages,
+final combine, in the chosen precision form.
+
+Printed (one JSON line): ms per projection, its relative error against an
+FP64 eigen-projection (rocSOLVER dsyevd on the same GPU), the roofline of the
+dominant kernel (the symmetric FP16 stage GEMM, timed with HIP events on its
+stream), the rocSOLVER ssyevd/dsyevd projection times, and the FP64 CPU oracle
+timed on a bounded sample and scaled to n = 10,000 by n^3.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per n=10k PSD projection at ≤1e-3 rel err; batched proj/s + p99 latency"
+PEAK = {"fp16": 2.5e15, "bf16": 2.5e15, "fp16_split": 2.5e15, "fp32": 157.3e12}
+DTYPE_NAME = {"fp16": "fp16", "bf16": "bf16", "fp16_split": "fp16", "fp32": "fp32"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# rocSOLVER eigen-projection (comparison leg, library calls)
+# ---------------------------------------------------------------------------
+class RocSolver:
+    def __init__(self, stream):
+        self.blas = ctypes.CDLL("librocblas.so")
+        self.sol = ctypes.CDLL("librocsolver.so")
+        self.h = ctypes.c_void_p()
+        assert self.blas.rocblas_create_handle(ctypes.byref(self.h)) == 0
+        assert self.blas.rocblas_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)) == 0
+
+    def projection(self, X, dtype):
+        """Q diag(max(w, 0)) Q^T with syevd (rocblas_evect_original, upper)."""
+        import torch
+        n = X.shape[0]
+        A = X.to(dtype).contiguous().clone()
+        w = torch.empty(n, dtype=dtype, device=X.device)
+        E = torch.empty(n, dtype=dtype, device=X.device)
+        info = torch.zeros(1, dtype=torch.int32, device=X.device)
+        fn = self.sol.rocsolver_dsyevd if dtype == torch.float64 else self.sol.rocsolver_ssyevd
+        st = fn(self.h, 211, 121, n, ctypes.c_void_p(A.data_ptr()), n, ctypes.c_void_p(w.data_ptr()),
+                ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(info.data_ptr()))
+        assert st == 0, st
+        # A holds eigenvectors in columns of the column-major buffer = rows of A
+        Q = A  # row i of the torch tensor = eigenvector i
+        P = (Q.t() * torch.clamp(w, min=0)) @ Q
+        return P, int(info.item())
+
+
+def time_rocsolver(rs, X, dtype, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P, info = rs.projection(X, dtype)
+    torch.cuda.synchronize()
+    return P, (time.perf_counter() - t0) / reps * 1e3, info
+
+
+# ---------------------------------------------------------------------------
+def gemm_roofline(n, mode, reps=10):
+    """Average duration of one symmetric stage GEMM launch (B = b A + c A A with
+    its fused epilogue) at the padded size of n, timed with HIP events on the
+    launch stream; achieved = algorithmic n^2 (n + 1) flops / duration."""
+    import torch
+    from paper_2507_09165_amd import psdproj as P
+    dt = "fp32" if mode == "fp32" else ("bf16" if mode == "bf16" else "fp16")
+    tdt = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[dt]
+    n_p = (n + 127) // 128 * 128
+    g = torch.Generator(device="cuda").manual_seed(1)
+    A = (torch.rand(n_p, n_p, device="cuda", generator=g) - 0.5) * (2.0 / np.sqrt(n_p))
+    A = ((A + A.t()) * 0.5).to(tdt)
+    D = torch.empty_like(A)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(st)
+    for _ in range(reps):
+        P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    flops = float(n) * n * (n + 1)
+    achieved = flops / (ms * 1e-3)
+    peak = PEAK[mode]
+    return {"kernel": f"gemm_sym_kernel<{dt}, stage epilogue>", "bound": "mfma", "achieved": achieved / 1e12,
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "ms_per_launch": ms, "flops_per_launch": flops, "n_padded": n_p}
+
+
+def cpu_baseline(mode, n_sample):
+    """The FP64 oracle (Algorithm 2 in numpy) timed on the host on one n_sample
+    GOE matrix, scaled to one n = 10,000 projection by (10000 / n_sample)^3."""
+    import oracle
+    from paper_2507_09165_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(d.get("num_threads", 1)) for d in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count() or 1
+    X = inputs.goe(n_sample, 4).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.project_poly(X, mode if mode != "fp16_split" else "fp16")
+    dt = time.perf_counter() - t0
+    scale = (10000.0 / n_sample) ** 3
+    return {"value": dt * 1e3 * scale, "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 oracle projection of a GOE n={n_sample} matrix took {dt:.2f} s; "
+                      f"scaled by (10000/{n_sample})^3"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--mode", default="fp16_split", choices=["fp16", "bf16", "fp16_split", "fp32"])
+    ap.add_argument("--input", default="goe", choices=["goe", "lowrank"])
+    ap.add_argument("--split-mask", type=lambda s: int(s, 0), default=0)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rocsolver", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X; this build has no multi-GPU path (--gpus must be 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_09165_amd import inputs
+    from paper_2507_09165_amd import psdproj as P
+
+    P.lib()
+    dev = torch.device("cuda:0")
+    n = args.n
+    log("generating input", args.input, n)
+    if args.input == "goe":
+        X32 = inputs.goe(n, 4)
+    else:
+        X32 = inputs.lowrank_noise(n, 5, 6)
+    X = torch.from_numpy(X32).to(dev)
+    del X32
+    out = torch.empty_like(X)
+    st = torch.cuda.current_stream()
+    opts = {"mode": args.mode, "split_mask": args.split_mask}
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        P.project_ex(X, out, stream=st, info=False, **opts)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(st)
+    for _ in range(args.steps):
+        P.project_ex(X, out, stream=st, info=False, **opts)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"projection: {ms:.3f} ms/step (wall {wall:.3f})")
+
+    _, info_t = P.project_ex(X, out, stream=st, **opts)
+    torch.cuda.synchronize()
+    info = P.read_info(info_t)
+
+    res = {"metric": METRIC, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": DTYPE_NAME[args.mode], "data": "synthetic",
+           "config": {"workload": f"single dense symmetric n={n} projection, "
+                                  f"{'GOE (seed 4)' if args.input == 'goe' else 'rank-500 PSD + noise (seeds 5, 6)'}",
+                      "n": n, "mode": args.mode, "input": args.input,
+                      "gemm_equivalents": P.gemm_count(**opts)},
+           "lambda": info["lambda"], "lanczos_steps": info["lanczos_steps"]}
+    flops = P.gemm_count(**opts) * float(n) * n * (n + 1)
+    res["algorithmic_tflops"] = flops / (ms * 1e-3) / 1e12
+
+    log("gemm roofline")
+    res["roofline"] = gemm_roofline(n, args.mode)
+
+    if not args.no_rocsolver or not args.no_check:
+        rs = RocSolver(st)
+        log("rocsolver dsyevd")
+        P64, t64, inf64 = time_rocsolver(rs, X, torch.float64)
+        roc = {"dsyevd_projection_ms": t64, "dsyevd_info": inf64}
+        if not args.no_check:
+            err = torch.linalg.norm(out.double() - P64) / torch.linalg.norm(P64)
+            res["rel_err_vs_fp64_evd"] = float(err)
+            log("rel err vs FP64 EVD", float(err))
+        del P64
+        if not args.no_rocsolver:
+            log("rocsolver ssyevd")
+            P32, t32, inf32 = time_rocsolver(rs, X, torch.float32)
+            roc.update({"ssyevd_projection_ms": t32, "ssyevd_info": inf32})
+            del P32
+        res["rocsolver"] = roc
+    res["paper_context"] = {"b200_fp16_ms": 54.8, "b200_fp32_emulated_ms": 416.0, "n": 10000}
+    if not args.no_cpu:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(args.mode, args.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * libpsdproj — factorization-free orthogonal projection of a dense symmetric
+ * matrix onto the positive semidefinite cone by composite polynomial
+ * filtering, for AMD Instinct MI355X (gfx950).
+ *
+ * The projection (Section 1, eq. (1)) is
+ *     Pi(X) = argmin_{Y >= 0} 1/2 ||Y - X||_F^2 = Q diag(max(lambda_i, 0)) Q^T.
+ * It is computed without an eigendecomposition (Algorithm 2):
+ *   1. lam = sqrt(sigma + ||X^2 q - sigma q||_2), (sigma, q) the largest Ritz
+ *      pair of a 20-step FP64 Lanczos run on X^2 (Theorem 2, Section 3.4);
+ *   2. X0 = X / lam;
+ *   3. X_t = f_t(X_{t-1}), t = 1..T, with the odd quintics
+ *      f_t(x) = a_t x + b_t x^3 + c_t x^5 of Table 1 (T = 10, single) or
+ *      Table 2 (T = 7, half), each stage evaluated with three matrix products;
+ *   4. return lam * X0 (I + X_T) / 2.
+ *
+ * Conventions shared by every entry point:
+ *   - X and out are DEVICE pointers owned by the caller, FP32, column-major
+ *     with leading dimension ld >= max(1, n). Only the upper triangle of X is
+ *     read (uplo = 'U'); both triangles of out are written and out is exactly
+ *     symmetric. out == X (in place) is allowed.
+ *   - Every call only enqueues work on `stream` (a hipStream_t; NULL is the
+ *     default stream) and returns. The return value reports argument, launch
+ *     and allocation errors only; numerical status (non-finite input, bound
+ *     fallback, lam) is written to device memory (psdproj_info).
+ *   - n == 0 is a no-op. X == 0 gives out == 0. A non-finite input leaves out
+ *     unmodified and sets psdproj_info.nonfinite.
+ *   - The library keeps a workspace per (device, stream), grown on demand
+ *     (growing synchronises that stream). Calls on one stream are ordered by
+ *     the stream; calls on different streams use different workspaces.
+ *   - No entry point reads device results back to the host.
+ */
+#ifndef PSDPROJ_H
+#define PSDPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *psdproj_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+    PSDPROJ_OK = 0,
+    PSDPROJ_ERR_INVALID_ARG = 1,
+    PSDPROJ_ERR_UNSUPPORTED = 2,
+    PSDPROJ_ERR_NO_MEMORY = 3,
+    PSDPROJ_ERR_HIP = 4,
+    PSDPROJ_ERR_REJECTED = 5,
+    PSDPROJ_ERR_CANCELLED = 6,
+    PSDPROJ_ERR_TIMEOUT = 7,
+    PSDPROJ_ERR_NOT_FOUND = 8,
+    PSDPROJ_ERR_PENDING = 9
+} psdproj_status;
+
+/* Compute precision of the filter products. Storage of X and out is FP32. */
+typedef enum {
+    PSDPROJ_MODE_FP32 = 0,       /* Table 1 refined (T = 10), FP32 MFMA, 31 products  */
+    PSDPROJ_MODE_FP16 = 1,       /* Table 2 refined (T = 7), FP16 MFMA, 22 products   */
+    PSDPROJ_MODE_BF16 = 2,       /* Table 2 refined (T = 7), BF16 MFMA, 22 products   */
+    PSDPROJ_MODE_FP16_SPLIT = 3  /* Table 2 refined, FP16 with hi+lo split operands in
+                                    the stages of split_mask and the final product   */
+} psdproj_mode;
+
+typedef struct {
+    int mode;                 /* psdproj_mode */
+    int lanczos_steps;        /* 0 -> 20 (Section 3.4); at most 32 */
+    uint32_t split_mask;      /* FP16_SPLIT: bit t set -> stage t+1 uses split
+                                 products; 0 -> library default */
+    int split_final;          /* FP16_SPLIT: -1 default, 0 plain, 1 split final product */
+    double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */
+    int force_bound_fallback; /* test hook: halve the Lanczos bound so that the
+                                 guard must replace it by ||X||_F */
+} psdproj_opts;
+
+/* Written on the device by psdproj_project_ex / psdproj_spectral_bound. */
+typedef struct {
+    double lambda;         /* bound used for the rescale */
+    double lanczos_lambda; /* sqrt(sigma + residual) before the guard */
+    double sigma;          /* largest Ritz value of X^2 */
+    double residual;       /* ||X^2 q - sigma q||_2 */
+    double fro_norm;       /* ||X||_F */
+    double colmax_norm;    /* max_j ||X e_j||_2 (lower bound on ||X||_2) */
+    int32_t lanczos_steps; /* Lanczos steps taken (early stop on breakdown) */
+    int32_t nonfinite;     /* input held Inf/NaN; out was not written */
+    int32_t fallback;      /* guard replaced an invalid Lanczos bound */
+    int32_t stages;        /* filter stages applied */
+} psdproj_info;
+
+/* Project X onto the PSD cone (Algorithm 2) in the given psdproj_mode.
+ * n >= 0, ld >= max(1, n); X, out device pointers (may alias).
+ * Returns PSDPROJ_OK, PSDPROJ_ERR_INVALID_ARG (bad n/ld/pointer/mode),
+ * PSDPROJ_ERR_NO_MEMORY (workspace) or PSDPROJ_ERR_HIP (launch failure). */
+int psdproj_project(int64_t n, int64_t ld, const float *X, float *out, int mode,
+                    psdproj_stream_t stream);
+
+/* As psdproj_project with options; info_dev (device memory, may be NULL)
+ * receives the numerical status once the stream reaches the end of the call. */
+int psdproj_project_ex(const psdproj_opts *opts, int64_t n, int64_t ld, const float *X,
+                       float *out, psdproj_stream_t stream, psdproj_info *info_dev);
+
+/* Only the spectral bound (steps 1-2 of Algorithm 2, Theorem 2): fills
+ * info_dev (device memory, required) for the upper triangle of X. */
+int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_steps,
+                           psdproj_stream_t stream, psdproj_info *info_dev);
+
+/* Batched projection of `count` independent matrices (host arrays of sizes,
+ * leading dimensions and device pointers). Matrices are independent; each
+ * result equals the one psdproj_project gives for that matrix alone. */
+int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld,
+                            const float *const *X, float *const *out, int mode,
+                            psdproj_stream_t stream);
+
+/* Device bytes of workspace a projection of size n in `mode` uses. */
+size_t psdproj_workspace_bytes(int64_t n, int mode);
+
+/* Number of n_p x n_p products (GEMM equivalents) a projection runs:
+ * 3 per stage + 1 for plain modes (22 half, 31 single); split products count
+ * 2 or 3 each. opts may be NULL (then `mode` defaults apply). */
+int psdproj_gemm_count(const psdproj_opts *opts, int mode);
+
+/* Host copy of the run-time coefficients of `mode` (rescale folded in):
+ * abc[3 t + 0..2] = (a_t, b_t, c_t). Returns T, or -1 for a bad mode or when
+ * cap < 3 T. */
+int psdproj_coefficients(int mode, double *abc, int cap);
+
+/* Free every cached workspace (synchronises the device). */
+int psdproj_release(void);
+
+const char *psdproj_status_string(int status);
+
+/* ---- kernel-level entry points (used by tests and tooling) ---------------
+ * psdproj_sym_gemm: D = alpha C0 + beta (L R) + gamma I on n_p x n_p
+ * symmetric work matrices (column-major, leading dimension ld >= n_p,
+ * n_p a multiple of 128) in dtype 0 = FP32, 1 = FP16, 2 = BF16. Only the upper
+ * tiles are computed and mirrored. *lo arguments may be NULL (unsplit);
+ * Dlo != NULL requests a split output. */
+int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo,
+                     const void *R, const void *Rlo, const void *C0, const void *C0lo,
+                     float alpha, float beta, float gamma, void *D, void *Dlo,
+                     psdproj_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSDPROJ_H */

@@ -1,0 +1,498 @@
+// Bandwidth-bound kernels of the projection: triangle mirror / rescale-and-cast,
+// and the FP64 Lanczos run that yields the spectral bound.
+//
+//  * mirror_cast: reads the upper triangle of X (column-major, ld) in 64 x 64
+//    tiles, writes the full symmetric matrix scaled by s (1 for the FP32 copy
+//    the Lanczos matvecs read, 1/lam for X0 = X / lam of Algorithm 2), rounded
+//    to the work precision, optionally as a hi + lo pair, zero-padded to n_p.
+//  * Lanczos on X^2 (Section 3.4 and Algorithm 2, first two steps): 20 steps
+//    of w = X (X v) in FP64 with full reorthogonalisation (two classical
+//    Gram-Schmidt passes), the largest Ritz pair (sigma, q) of the tridiagonal,
+//    and the bound lam = sqrt(sigma + ||X (X q) - sigma q||) of Theorem 2.
+//    The first matvec also produces the column norms: ||X||_F and the lower
+//    bound max_j ||X e_j|| that guards the heuristic bound.
+// All reductions are fixed-order (no floating-point atomics), so results are
+// bitwise reproducible run to run.
+#include <math.h>
+
+#include "aux_kernels.hpp"
+#include "common.hpp"
+
+namespace psd {
+
+// ---------------------------------------------------------------------------
+// mirror / rescale / cast
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T cvt(float v) { return (T)v; }
+
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(256) void mirror_cast_kernel(const float *__restrict__ X, int64_t ldx, int64_t n,
+                                                          const Scalars *scal, int use_inv_lam, T *__restrict__ Ohi,
+                                                          T *__restrict__ Olo, int64_t ldo, float lo_scale) {
+    __shared__ float tile[64][65];
+    // upper-triangle tile pairs over the padded size, column by column
+    const int t = blockIdx.x;
+    int bj = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
+    while (bj * (bj + 1) / 2 > t) --bj;
+    const int bi = t - bj * (bj + 1) / 2;
+    const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
+    const float s = use_inv_lam ? (float)scal->inv_lam : 1.0f;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    // load: element (i0 + tx, j0 + c) = X[(j0 + c) * ldx + i0 + tx], upper part only
+    for (int c = ty; c < 64; c += 4) {
+        const int64_t i = i0 + tx, j = j0 + c;
+        float v = 0.0f;
+        if (i < n && j < n && i <= j) v = X[j * ldx + i];
+        tile[tx][c] = v;
+    }
+    __syncthreads();
+    if (bi == bj) {  // complete the diagonal tile from its upper half
+        for (int c = ty; c < 64; c += 4)
+            if (tx > c) tile[tx][c] = tile[c][tx];
+        __syncthreads();
+    }
+    // direct write: O(i0 + tx, j0 + c) at column j0 + c
+    for (int c = ty; c < 64; c += 4) {
+        const float v = tile[tx][c] * s;
+        const T hi = cvt<T>(v);
+        Ohi[(j0 + c) * ldo + i0 + tx] = hi;
+        if constexpr (SPLIT) Olo[(j0 + c) * ldo + i0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
+    }
+    if (bi == bj) return;
+    // mirrored write: O(j0 + tx, i0 + c) = tile[c][tx]
+    for (int c = ty; c < 64; c += 4) {
+        const float v = tile[c][tx] * s;
+        const T hi = cvt<T>(v);
+        Ohi[(i0 + c) * ldo + j0 + tx] = hi;
+        if constexpr (SPLIT) Olo[(i0 + c) * ldo + j0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
+    }
+}
+
+template <typename T, bool SPLIT>
+static hipError_t mirror_cast_t(const float *X, int64_t ldx, int64_t n, int64_t n_out, const Scalars *scal,
+                                int use_inv_lam, void *Ohi, void *Olo, int64_t ldo, float lo_scale, hipStream_t s) {
+    const int64_t nt = (n_out + 63) / 64;
+    const int64_t ntiles = nt * (nt + 1) / 2;
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((mirror_cast_kernel<T, SPLIT>), dim3((unsigned)ntiles), dim3(256), 0, s, X, ldx, n, scal,
+                       use_inv_lam, (T *)Ohi, (T *)Olo, ldo, lo_scale);
+    return hipGetLastError();
+}
+
+hipError_t mirror_cast(const float *X, int64_t ldx, int64_t n, int64_t n_out, const Scalars *scal, int use_inv_lam,
+                       int dtype, void *Ohi, void *Olo, int64_t ldo, hipStream_t s) {
+    if (n_out % 64) return hipErrorInvalidValue;
+    switch (dtype) {
+        case 0: return mirror_cast_t<float, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
+        case 1:
+            return Olo ? mirror_cast_t<f16, true>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, Olo, ldo, 2048.0f, s)
+                       : mirror_cast_t<f16, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
+        case 2:
+            return Olo ? mirror_cast_t<bf16, true>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, Olo, ldo, 1.0f, s)
+                       : mirror_cast_t<bf16, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
+// z_i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15); v_i = 2 (z_i >> 11) 2^-53 - 1.
+__device__ __forceinline__ double start_entry(uint64_t i, uint64_t seed) {
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+constexpr int kMvCols = 4;    // output entries per wave
+constexpr int kMvWaves = 4;   // waves per block
+
+// y[i] = scale * sum_j X(j, i) v[j] for the symmetric Xf (column i == row i).
+// Optionally colsq[i] = sum_j X(j, i)^2. Skips all work once the breakdown
+// flag is set (stop_on_flag).
+__global__ __launch_bounds__(256) void matvec_kernel(const float *__restrict__ Xf, int64_t ldx, int64_t n,
+                                                     const double *__restrict__ v, const double *vscale,
+                                                     double *__restrict__ y, double *__restrict__ colsq,
+                                                     const Scalars *scal, int stop_on_flag) {
+    if (stop_on_flag && scal->stop) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t c0 = ((int64_t)blockIdx.x * kMvWaves + wave) * kMvCols;
+    double acc[kMvCols], sq[kMvCols];
+#pragma unroll
+    for (int c = 0; c < kMvCols; ++c) acc[c] = sq[c] = 0.0;
+    const bool vec4 = ((ldx & 3) == 0);
+    if (vec4) {
+        const int64_t n4 = n & ~(int64_t)3;
+        for (int64_t k = (int64_t)lane * 4; k < n4; k += 256) {
+            const double v0 = v[k], v1 = v[k + 1], v2 = v[k + 2], v3 = v[k + 3];
+#pragma unroll
+            for (int c = 0; c < kMvCols; ++c) {
+                const int64_t col = c0 + c;
+                if (col < n) {
+                    const float4 x = *(const float4 *)(Xf + col * ldx + k);
+                    acc[c] += (double)x.x * v0 + (double)x.y * v1 + (double)x.z * v2 + (double)x.w * v3;
+                    if (colsq) sq[c] += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
+                }
+            }
+        }
+        for (int64_t k = n4 + lane; k < n; k += 64) {
+            const double vk = v[k];
+#pragma unroll
+            for (int c = 0; c < kMvCols; ++c) {
+                const int64_t col = c0 + c;
+                if (col < n) {
+                    const double x = Xf[col * ldx + k];
+                    acc[c] += x * vk;
+                    if (colsq) sq[c] += x * x;
+                }
+            }
+        }
+    } else {
+        for (int64_t k = lane; k < n; k += 64) {
+            const double vk = v[k];
+#pragma unroll
+            for (int c = 0; c < kMvCols; ++c) {
+                const int64_t col = c0 + c;
+                if (col < n) {
+                    const double x = Xf[col * ldx + k];
+                    acc[c] += x * vk;
+                    if (colsq) sq[c] += x * x;
+                }
+            }
+        }
+    }
+    const double sc = vscale ? *vscale : 1.0;
+#pragma unroll
+    for (int c = 0; c < kMvCols; ++c) {
+        const double a = wave_sum(acc[c]);
+        const double q = colsq ? wave_sum(sq[c]) : 0.0;
+        const int64_t col = c0 + c;
+        if (lane == 0 && col < n) {
+            y[col] = a * sc;
+            if (colsq) colsq[col] = q;
+        }
+    }
+}
+
+constexpr int kRows = 256;  // rows per block in the vector kernels
+
+// Block reduction of NV doubles per thread into out[0..NV) (thread 0 holds it).
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double *sh /* [4][NV] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = sh[k] + sh[NV + k] + sh[2 * NV + k] + sh[3 * NV + k];
+}
+
+// Sum of the per-block partials part[b * stride + k], b = 0..nb-1, in order.
+__device__ __forceinline__ double sum_partials(const double *part, int nb, int stride, int k) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * stride + k];
+    return s;
+}
+
+// Start vector: V[:, 0] = v / ||v||. Pass 0 writes v and the partial norms,
+// pass 1 normalises.
+__global__ __launch_bounds__(256) void lz_start_kernel(double *V, int64_t n, double *part, int pass, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    __shared__ double sh[4];
+    if (pass == 0) {
+        double x[1] = {0.0};
+        if (i < n) {
+            const double e = start_entry((uint64_t)i, seed);
+            V[i] = e;
+            x[0] = e * e;
+        }
+        block_reduce<1>(x, sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+    } else {
+        const double nrm = sqrt(sum_partials(part, gridDim.x, kMaxLanczos, 0));
+        if (i < n) V[i] = V[i] / nrm;
+    }
+}
+
+// Orthogonalisation pass of step j over rows of this block.
+//  pass 0: part <- V[:, 0..j]^T w (first classical Gram-Schmidt pass)
+//  pass 1: h = sum(part); alpha_j = h_j; w -= V h; part <- V^T w (second pass)
+//  pass 2: h = sum(part); w -= V h; part <- ||w||^2
+__global__ __launch_bounds__(256) void lz_orth_kernel(const double *V, int64_t n, int j, double *w, const double *part_in,
+                                                      double *part_out, Scalars *scal, int pass) {
+    if (scal->stop) return;
+    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    const int nb = gridDim.x;
+    __shared__ double hsh[kMaxLanczos];
+    __shared__ double red[4 * kMaxLanczos];
+    double wi = (i < n) ? w[i] : 0.0;
+    if (pass > 0) {
+        if (threadIdx.x <= j) hsh[threadIdx.x] = sum_partials(part_in, nb, kMaxLanczos, threadIdx.x);
+        __syncthreads();
+        if (pass == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+            scal->alpha[j] = hsh[j];
+            scal->amax = fmax(scal->amax, fabs(hsh[j]));
+        }
+        if (i < n) {
+            double s = 0.0;
+            for (int k = 0; k <= j; ++k) s += V[(int64_t)k * n + i] * hsh[k];
+            wi -= s;
+            w[i] = wi;
+        }
+    }
+    if (pass < 2) {
+        double h[kMaxLanczos];
+#pragma unroll
+        for (int k = 0; k < kMaxLanczos; ++k) h[k] = (k <= j && i < n) ? V[(int64_t)k * n + i] * wi : 0.0;
+        block_reduce<kMaxLanczos>(h, red);
+        if (threadIdx.x == 0)
+            for (int k = 0; k <= j; ++k) part_out[(int64_t)blockIdx.x * kMaxLanczos + k] = h[k];
+    } else {
+        double x[1] = {wi * wi};
+        block_reduce<1>(x, red);
+        if (threadIdx.x == 0) part_out[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+    }
+}
+
+// beta_j = ||w||; stop if beta_j <= 1e-13 max|alpha| or j is the last step,
+// else V[:, j+1] = w / beta_j.
+__global__ __launch_bounds__(256) void lz_next_kernel(double *V, int64_t n, int j, int steps, const double *w,
+                                                      const double *part, Scalars *scal) {
+    if (scal->stop) return;
+    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    const double beta = sqrt(sum_partials(part, gridDim.x, kMaxLanczos, 0));
+    const bool stop = (j == steps - 1) || !(beta > 1e-13 * scal->amax);
+    if (!stop && i < n) V[(int64_t)(j + 1) * n + i] = w[i] / beta;
+    // Every block has read scal->stop/amax above; the flag update below is
+    // seen only by later kernels on the stream.
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal->k = j + 1;
+        scal->beta_last = beta;
+        if (!stop) scal->beta[j] = beta;
+    }
+    if (stop && blockIdx.x == 0 && threadIdx.x == 0) scal->stop = 1;
+}
+
+// Largest eigenpair of the k x k tridiagonal T (alpha, beta): bisection on the
+// Sturm count for sigma, then inverse iteration with a dense partially pivoted
+// LU for the eigenvector s (k <= 32, one thread).
+__global__ void lz_ritz_kernel(Scalars *scal) {
+    if (threadIdx.x != 0) return;
+    const int k = scal->k;
+    const double *al = scal->alpha, *be = scal->beta;
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
+        lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
+        hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
+    }
+    const double scale_t = fmax(fabs(lo), fabs(hi));
+    const double tiny = 1e-300 + 1e-30 * scale_t;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        int cnt = 0;  // number of eigenvalues < mid
+        double d = al[0] - mid;
+        if (d == 0.0) d = -tiny;
+        cnt += d < 0.0;
+        for (int i = 1; i < k; ++i) {
+            d = al[i] - mid - be[i - 1] * be[i - 1] / d;
+            if (d == 0.0) d = -tiny;
+            cnt += d < 0.0;
+        }
+        if (cnt == k) hi = mid; else lo = mid;
+    }
+    const double sigma = 0.5 * (lo + hi);
+    scal->sigma = sigma;
+    // inverse iteration on (T - sigma I)
+    double M[kMaxLanczos][kMaxLanczos];
+    int piv[kMaxLanczos];
+    for (int r = 0; r < k; ++r)
+        for (int c = 0; c < k; ++c) M[r][c] = 0.0;
+    for (int r = 0; r < k; ++r) {
+        M[r][r] = al[r] - sigma;
+        if (r + 1 < k) M[r][r + 1] = M[r + 1][r] = be[r];
+    }
+    const double eps_p = 1e-15 * (scale_t > 0.0 ? scale_t : 1.0);
+    for (int c = 0; c < k; ++c) {
+        int p = c;
+        for (int r = c + 1; r < k; ++r)
+            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+        piv[c] = p;
+        if (p != c)
+            for (int q = 0; q < k; ++q) {
+                const double tmp = M[c][q]; M[c][q] = M[p][q]; M[p][q] = tmp;
+            }
+        if (fabs(M[c][c]) < eps_p) M[c][c] = (M[c][c] < 0.0 ? -eps_p : eps_p);
+        for (int r = c + 1; r < k; ++r) {
+            const double f = M[r][c] / M[c][c];
+            M[r][c] = f;
+            for (int q = c + 1; q < k; ++q) M[r][q] -= f * M[c][q];
+        }
+    }
+    double x[kMaxLanczos];
+    for (int i = 0; i < k; ++i) x[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        for (int c = 0; c < k; ++c) {  // apply the row swaps and L^-1
+            const int p = piv[c];
+            if (p != c) { const double tmp = x[c]; x[c] = x[p]; x[p] = tmp; }
+            for (int r = c + 1; r < k; ++r) x[r] -= M[r][c] * x[c];
+        }
+        for (int r = k - 1; r >= 0; --r) {  // U^-1
+            double s = x[r];
+            for (int q = r + 1; q < k; ++q) s -= M[r][q] * x[q];
+            x[r] = s / M[r][r];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += x[i] * x[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < k; ++i) x[i] = nrm > 0.0 ? x[i] / nrm : (i == 0 ? 1.0 : 0.0);
+    }
+    for (int i = 0; i < kMaxLanczos; ++i) scal->s[i] = i < k ? x[i] : 0.0;
+}
+
+// q = V[:, 0..k) s; part <- ||q||^2
+__global__ __launch_bounds__(256) void lz_q_kernel(const double *V, int64_t n, double *q, double *part, const Scalars *scal) {
+    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    __shared__ double red[4];
+    double qi = 0.0;
+    if (i < n) {
+        for (int k = 0; k < scal->k; ++k) qi += V[(int64_t)k * n + i] * scal->s[k];
+        q[i] = qi;
+    }
+    double x[1] = {qi * qi};
+    block_reduce<1>(x, red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+}
+
+__global__ void lz_qnorm_kernel(const double *part, int nb, Scalars *scal) {
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(sum_partials(part, nb, kMaxLanczos, 0));
+    scal->qnorm_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+}
+
+// part <- ||w - sigma q_hat||^2 with q_hat = q * qnorm_inv
+__global__ __launch_bounds__(256) void lz_resid_kernel(const double *w, const double *q, int64_t n, double *part,
+                                                       const Scalars *scal) {
+    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    __shared__ double red[4];
+    double r = 0.0;
+    if (i < n) r = w[i] - scal->sigma * (q[i] * scal->qnorm_inv);
+    double x[1] = {r * r};
+    block_reduce<1>(x, red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+}
+
+// Frobenius norm and column-norm maximum from colsq, residual from the
+// partials, then lam = sqrt(sigma + r) (Theorem 2), guarded: if lam is not at
+// least the largest column norm (a lower bound on ||X||_2) the Frobenius norm
+// is used; lam is capped by the Frobenius norm (also an upper bound).
+__global__ __launch_bounds__(256) void lz_bound_kernel(const double *colsq, int64_t n, const double *part, int nb,
+                                                       Scalars *scal, int force_fallback) {
+    __shared__ double sh_sum[256], sh_max[256];
+    double s = 0.0, m = 0.0;
+    int bad = 0;
+    // fixed per-thread stride, then a fixed-order tree: deterministic
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double c = colsq[i];
+        s += c;
+        if (!(c <= 1.7e308)) bad = 1;  // NaN or Inf
+        m = fmax(m, c);
+    }
+    sh_sum[threadIdx.x] = s;
+    sh_max[threadIdx.x] = bad ? INFINITY : m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh_sum[threadIdx.x] += sh_sum[threadIdx.x + w];
+            sh_max[threadIdx.x] = fmax(sh_max[threadIdx.x], sh_max[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double fro2 = sh_sum[0], colmax2 = sh_max[0];
+    scal->fro2 = fro2;
+    scal->colmax2 = colmax2;
+    const int nonfinite = !(fro2 <= 1.7e308) || !(colmax2 <= 1.7e308);
+    scal->nonfinite = nonfinite;
+    const double r = sqrt(sum_partials(part, nb, kMaxLanczos, 0));
+    scal->resid = r;
+    const double lz = sqrt(fmax(scal->sigma + r, 0.0));
+    scal->lanczos_lam = lz;
+    const double fro = sqrt(fro2), colmax = sqrt(colmax2);
+    double lam = lz;
+    int fb = 0;
+    if (force_fallback) lam = 0.5 * lz;  // test hook: an invalid bound
+    if (!(lam >= colmax)) { lam = fro; fb = 1; }
+    if (lam > fro) lam = fro;
+    scal->fallback = fb;
+    scal->lam = nonfinite ? 0.0 : lam;
+    scal->inv_lam = (nonfinite || !(lam > 0.0)) ? 0.0 : 1.0 / lam;
+}
+
+__global__ void scal_init_kernel(Scalars *scal) {
+    if (threadIdx.x == 0) {
+        Scalars z = {};
+        *scal = z;
+    }
+}
+
+hipError_t spectral_bound(const float *Xf, int64_t ldx, int64_t n, int steps, uint64_t seed, LanczosWork wk,
+                          Scalars *scal, int force_fallback, hipStream_t s) {
+    if (steps < 1 || steps > kMaxLanczos) return hipErrorInvalidValue;
+    const unsigned nbv = (unsigned)((n + kRows - 1) / kRows);
+    const unsigned nbm = (unsigned)((n + kMvCols * kMvWaves - 1) / (kMvCols * kMvWaves));
+    if (nbv == 0) return hipSuccess;
+    double *V = wk.V, *u = wk.u, *w = wk.w, *pa = wk.part_a, *pb = wk.part_b;
+    hipLaunchKernelGGL(scal_init_kernel, dim3(1), dim3(64), 0, s, scal);
+    hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 0, seed);
+    hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 1, seed);
+    for (int j = 0; j < steps; ++j) {
+        hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, V + (int64_t)j * n,
+                           (const double *)nullptr, u, j == 0 ? wk.colsq : (double *)nullptr, scal, 1);
+        hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)u,
+                           (const double *)nullptr, w, (double *)nullptr, scal, 1);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w,
+                           (const double *)nullptr, pa, scal, 0);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pa,
+                           pb, scal, 1);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pb,
+                           pa, scal, 2);
+        hipLaunchKernelGGL(lz_next_kernel, dim3(nbv), dim3(256), 0, s, V, n, j, steps, (const double *)w,
+                           (const double *)pa, scal);
+    }
+    hipLaunchKernelGGL(lz_ritz_kernel, dim3(1), dim3(64), 0, s, scal);
+    hipLaunchKernelGGL(lz_q_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, u, pa, (const Scalars *)scal);
+    hipLaunchKernelGGL(lz_qnorm_kernel, dim3(1), dim3(64), 0, s, (const double *)pa, (int)nbv, scal);
+    hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)u,
+                       (const double *)&scal->qnorm_inv, w, (double *)nullptr, scal, 0);
+    hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)w,
+                       (const double *)nullptr, wk.w2, (double *)nullptr, scal, 0);
+    hipLaunchKernelGGL(lz_resid_kernel, dim3(nbv), dim3(256), 0, s, (const double *)wk.w2, (const double *)u, n, pa,
+                       (const Scalars *)scal);
+    hipLaunchKernelGGL(lz_bound_kernel, dim3(1), dim3(256), 0, s, (const double *)wk.colsq, n, (const double *)pa,
+                       (int)nbv, scal, force_fallback);
+    return hipGetLastError();
+}
+
+size_t lanczos_work_doubles(int64_t n, int steps) {
+    const int64_t nbv = (n + kRows - 1) / kRows;
+    return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + 64);
+}
+
+}  // namespace psd

@@ -1,0 +1,210 @@
+"""ctypes binding of libpsdproj (argument marshalling only).
+
+Every step of the projection runs in the HIP library; PyTorch only provides
+device memory (tensor ``data_ptr()``) and the stream
+(``torch.cuda.current_stream().cuda_stream``). If the library is not built the
+import fails loudly — there is no fallback path.
+
+Layout note: a row-major torch tensor ``T`` of shape (n, n) with stride (n, 1)
+is the column-major matrix ``T^T`` with leading dimension n. For symmetric
+inputs the two coincide; the library reads the upper triangle of the
+column-major matrix, i.e. ``torch.tril(T)`` in torch indexing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsdproj.so")
+
+MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3}
+DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
+          4: "HIP error", 5: "rejected", 6: "cancelled", 7: "timeout", 8: "not found",
+          9: "pending"}
+
+
+class PsdprojError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
+                ("split_mask", ctypes.c_uint32), ("split_final", ctypes.c_int),
+                ("lambda_override", ctypes.c_double), ("force_bound_fallback", ctypes.c_int)]
+
+
+INFO_DTYPE = np.dtype([("lambda", "<f8"), ("lanczos_lambda", "<f8"), ("sigma", "<f8"),
+                       ("residual", "<f8"), ("fro_norm", "<f8"), ("colmax_norm", "<f8"),
+                       ("lanczos_steps", "<i4"), ("nonfinite", "<i4"), ("fallback", "<i4"),
+                       ("stages", "<i4")])
+assert INFO_DTYPE.itemsize == 64
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python paper_2507_09165_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, vp, c_int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    L.psdproj_project.argtypes = [i64, i64, vp, vp, c_int, vp]
+    L.psdproj_project_ex.argtypes = [ctypes.POINTER(Opts), i64, i64, vp, vp, vp, vp]
+    L.psdproj_spectral_bound.argtypes = [i64, i64, vp, c_int, vp, vp]
+    L.psdproj_project_batched.argtypes = [c_int, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp), c_int, vp]
+    L.psdproj_workspace_bytes.argtypes = [i64, c_int]
+    L.psdproj_workspace_bytes.restype = ctypes.c_size_t
+    L.psdproj_gemm_count.argtypes = [ctypes.POINTER(Opts), c_int]
+    L.psdproj_coefficients.argtypes = [c_int, ctypes.POINTER(ctypes.c_double), c_int]
+    L.psdproj_release.argtypes = []
+    L.psdproj_status_string.argtypes = [c_int]
+    L.psdproj_status_string.restype = ctypes.c_char_p
+    L.psdproj_sym_gemm.argtypes = [c_int, i64, i64, vp, vp, vp, vp, vp, vp,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    for name in ("psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
+                 "psdproj_project_batched", "psdproj_gemm_count", "psdproj_coefficients",
+                 "psdproj_release", "psdproj_sym_gemm"):
+        getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise PsdprojError(st, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mode(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _check_matrix(X, name="X"):
+    import torch
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if X.dim() != 2 or X.shape[0] != X.shape[1]:
+        raise ValueError(f"{name} must be square")
+    if X.stride(1) != 1 or X.stride(0) < max(1, X.shape[0]):
+        raise ValueError(f"{name} must have unit stride in its last dimension")
+    return X.shape[0], X.stride(0)
+
+
+def make_opts(mode="fp16", lanczos_steps=0, split_mask=0, split_final=-1, lambda_override=0.0,
+              force_bound_fallback=False) -> Opts:
+    return Opts(_mode(mode), int(lanczos_steps), int(split_mask), int(split_final),
+                float(lambda_override), int(bool(force_bound_fallback)))
+
+
+def project(X, out=None, mode="fp16", stream=None):
+    """out = Pi(X) (Algorithm 2). X: (n, n) float32 CUDA tensor; out may be X."""
+    import torch
+    n, ld = _check_matrix(X)
+    if out is None:
+        out = torch.empty_like(X)
+    n2, ldo = _check_matrix(out, "out")
+    if n2 != n or ldo != ld:
+        raise ValueError("out must match X in shape and stride")
+    _check(lib().psdproj_project(n, ld, _ptr(X), _ptr(out), _mode(mode), _stream(stream)),
+           "psdproj_project")
+    return out
+
+
+def project_ex(X, out=None, stream=None, info=True, **opts):
+    """Projection with options; returns (out, info_tensor). Call
+    ``read_info(info_tensor)`` after synchronising to get a dict."""
+    import torch
+    n, ld = _check_matrix(X)
+    if out is None:
+        out = torch.empty_like(X)
+    o = make_opts(**opts)
+    info_t = torch.zeros(64, dtype=torch.uint8, device=X.device) if info else None
+    _check(lib().psdproj_project_ex(ctypes.byref(o), n, ld, _ptr(X), _ptr(out), _stream(stream),
+                                    _ptr(info_t)), "psdproj_project_ex")
+    return out, info_t
+
+
+def read_info(info_t) -> dict:
+    raw = info_t.cpu().numpy().tobytes()
+    rec = np.frombuffer(raw, dtype=INFO_DTYPE)[0]
+    return {k: rec[k].item() for k in INFO_DTYPE.names}
+
+
+def spectral_bound(X, lanczos_steps=20, stream=None) -> dict:
+    import torch
+    n, ld = _check_matrix(X)
+    info_t = torch.zeros(64, dtype=torch.uint8, device=X.device)
+    _check(lib().psdproj_spectral_bound(n, ld, _ptr(X), int(lanczos_steps), _stream(stream),
+                                        _ptr(info_t)), "psdproj_spectral_bound")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return read_info(info_t)
+
+
+def project_batched(Xs, outs=None, mode="bf16", stream=None):
+    import torch
+    if outs is None:
+        outs = [torch.empty_like(X) for X in Xs]
+    cnt = len(Xs)
+    ns = (ctypes.c_int64 * cnt)()
+    lds = (ctypes.c_int64 * cnt)()
+    xp = (ctypes.c_void_p * cnt)()
+    op = (ctypes.c_void_p * cnt)()
+    for i, (X, O) in enumerate(zip(Xs, outs)):
+        n, ld = _check_matrix(X)
+        ns[i], lds[i], xp[i], op[i] = n, ld, X.data_ptr(), O.data_ptr()
+    _check(lib().psdproj_project_batched(cnt, ns, lds, xp, op, _mode(mode), _stream(stream)),
+           "psdproj_project_batched")
+    return outs
+
+
+def workspace_bytes(n: int, mode="fp16") -> int:
+    return int(lib().psdproj_workspace_bytes(int(n), _mode(mode)))
+
+
+def gemm_count(mode="fp16", **opts) -> int:
+    o = make_opts(mode=mode, **opts)
+    return int(lib().psdproj_gemm_count(ctypes.byref(o), _mode(mode)))
+
+
+def coefficients(mode="fp16") -> np.ndarray:
+    buf = (ctypes.c_double * 96)()
+    T = lib().psdproj_coefficients(_mode(mode), buf, 96)
+    if T < 0:
+        raise PsdprojError(1, "psdproj_coefficients")
+    return np.array(buf[: 3 * T]).reshape(T, 3)
+
+
+def release():
+    _check(lib().psdproj_release(), "psdproj_release")
+
+
+def sym_gemm(dtype, L, R, D, Llo=None, Rlo=None, C0=None, C0lo=None, Dlo=None,
+             alpha=0.0, beta=1.0, gamma=0.0, stream=None):
+    """D = alpha C0 + beta L R + gamma I on n_p x n_p symmetric work matrices."""
+    n_p = L.shape[0]
+    ld = L.stride(0)
+    _check(lib().psdproj_sym_gemm(DTYPES[dtype], n_p, ld, _ptr(L), _ptr(Llo), _ptr(R), _ptr(Rlo),
+                                  _ptr(C0), _ptr(C0lo), float(alpha), float(beta), float(gamma),
+                                  _ptr(D), _ptr(Dlo), _stream(stream)), "psdproj_sym_gemm")
+    return D

@@ -1,0 +1,190 @@
+"""End-to-end parity of the HIP projection with the FP64 oracle.
+
+The oracle evaluates Algorithm 2 in FP64 with the device's spectral bound
+(lambda_override), so both sides compute the same function; the bound itself
+is compared separately. Tolerances (relative Frobenius):
+  FP32 <= 1e-5, FP16 <= 5e-3 against the polynomial oracle;
+  the split form additionally <= 1e-3 against the exact projection.
+BF16 (8-bit significand, u = 2^-9) sits near 8x the FP16 error; its plain
+form is held to 3e-2 and reported.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_09165_amd import inputs
+from paper_2507_09165_amd import psdproj as P
+from gpu_util import dev, rel_fro, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_POLY = {"fp32": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "bf16": 3e-2}
+
+
+def _run(X32, mode, **opts):
+    import torch
+    Xg = to_dev(X32)
+    out, info_t = P.project_ex(Xg, mode=mode, **opts)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), P.read_info(info_t)
+
+
+def _check_case(name, X32, mode, exact=None):
+    say("parity", name, mode, X32.shape[0])
+    out, info = _run(X32, mode)
+    X = X32.astype(np.float64)
+    ref, _ = oracle.project_poly(X, mode, lam=info["lambda"])
+    e_poly = rel_fro(out, ref)
+    msg = f"{name} {mode}: vs poly {e_poly:.3e}"
+    if exact is not None:
+        e_ex = rel_fro(out, exact)
+        msg += f" vs exact {e_ex:.3e}"
+    say("  ", msg, "lam", info["lambda"])
+    np.testing.assert_array_equal(out, out.T)
+    assert info["nonfinite"] == 0 and info["fallback"] == 0
+    assert e_poly <= TOL_POLY[mode], msg
+    return out, info
+
+
+def test_c1_fp32_n256():
+    """n = 256, X = Q diag(lam) Q^T, lam ~ U[-1, 1], FP32 composite, one call."""
+    X32, Q, lam = inputs.constructed(256, 0, 1)
+    exact = oracle.project_exact(X32.astype(np.float64))
+    out, info = _check_case("C1", X32, "fp32", exact)
+    assert rel_fro(out, exact) < 2e-5
+
+
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp32"])
+@pytest.mark.parametrize("n", [200, 777])
+def test_goe_ragged(mode, n):
+    X32 = inputs.goe(n, 2)
+    exact = oracle.project_exact_eigh(X32.astype(np.float64))
+    out, _ = _check_case("goe", X32, mode, exact)
+    if mode == "fp16_split":
+        assert rel_fro(out, exact) <= 1e-3
+
+
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split"])
+def test_clustered_n1000(mode):
+    X32, Q, lam = inputs.clustered(1000, 3)
+    exact = oracle.project_spectral(Q, lam, lambda l: np.maximum(l, 0.0))
+    _check_case("clustered", X32, mode, exact)
+
+
+def test_lowrank_noise_n640():
+    X32 = inputs.lowrank_noise(640, 5, 6, rank=32)
+    exact = oracle.project_exact_eigh(X32.astype(np.float64))
+    for mode in ("fp16", "fp16_split"):
+        _check_case("lowrank", X32, mode, exact)
+
+
+def test_bound_matches_oracle_in_projection():
+    X32 = inputs.goe(500, 9)
+    _, info = _run(X32, "fp16")
+    ref = oracle.spectral_bound(X32.astype(np.float64))
+    assert abs(info["lambda"] - ref["lam"]) <= 1e-9 * ref["lam"]
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_zero_matrix_gives_zero():
+    import torch
+    X = torch.zeros(300, 300, device=dev())
+    out = torch.full_like(X, 7.0)
+    P.project(X, out, mode="fp16")
+    torch.cuda.synchronize()
+    assert not out.any()
+
+
+def test_n1_and_n2():
+    for x in (2.5, -0.5):
+        out, info = _run(np.array([[x]], dtype=np.float32), "fp32")
+        assert abs(info["lambda"] - abs(x)) < 1e-6 * abs(x)
+        want = abs(x) * oracle.g_scalar(np.sign(x), "fp32")
+        assert abs(out[0, 0] - want) <= 1e-5 * abs(x)
+    X2 = np.array([[1.0, 2.0], [2.0, -1.0]], dtype=np.float32)
+    out, info = _run(X2, "fp32")
+    exact = oracle.project_exact(X2.astype(np.float64))
+    assert rel_fro(out, exact) < 2e-5
+
+
+def test_empty_is_noop():
+    assert P.lib().psdproj_project(0, 1, None, None, 1, None) == 0
+
+
+def test_nonfinite_input_leaves_output_untouched():
+    import torch
+    X32 = inputs.goe(150, 4)
+    X32[3, 7] = X32[7, 3] = np.nan
+    Xg = to_dev(X32)
+    out = torch.full_like(Xg, 3.0)
+    _, info_t = P.project_ex(Xg, out, mode="fp16")
+    torch.cuda.synchronize()
+    info = P.read_info(info_t)
+    assert info["nonfinite"] == 1
+    assert torch.all(out == 3.0)
+
+
+def test_in_place_and_padded_ld():
+    import torch
+    n, ld = 333, 400
+    X32 = inputs.goe(n, 12)
+    buf = torch.full((n, ld), 1e30, device=dev(), dtype=torch.float32)
+    buf[:, :n] = to_dev(X32)
+    Xv = buf[:, :n]
+    ref_out, info = _run(X32, "fp16")
+    P.project(Xv, Xv, mode="fp16")  # in place, ld = 400
+    torch.cuda.synchronize()
+    got = Xv.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(got, ref_out)
+    assert torch.all(buf[:, n:] == 1e30)
+
+
+def test_reads_upper_triangle_only():
+    import torch
+    n = 260
+    X32 = inputs.goe(n, 13)
+    ref_out, _ = _run(X32, "fp16")
+    Y = X32.copy()
+    # column-major upper triangle == row-major lower triangle (torch indexing)
+    Y[np.triu_indices(n, 1)] = 1e3
+    out, _ = _run(Y, "fp16")
+    np.testing.assert_array_equal(out, ref_out)
+
+
+def test_deterministic_repeat():
+    X32 = inputs.goe(700, 14)
+    a, _ = _run(X32, "fp16")
+    b, _ = _run(X32, "fp16")
+    np.testing.assert_array_equal(a, b)
+
+
+def test_forced_fallback_uses_frobenius():
+    X32 = inputs.goe(300, 15)
+    out, info = _run(X32, "fp32", force_bound_fallback=True)
+    fro = np.linalg.norm(X32.astype(np.float64))
+    assert info["fallback"] == 1
+    assert abs(info["lambda"] - fro) <= 1e-9 * fro
+    ref, _ = oracle.project_poly(X32.astype(np.float64), "fp32", lam=info["lambda"])
+    assert rel_fro(out, ref) < 1e-5
+
+
+def test_lambda_override():
+    X32 = inputs.goe(256, 16)
+    lam = 2.5
+    out, info = _run(X32, "fp32", lambda_override=lam)
+    assert info["lambda"] == lam
+    ref, _ = oracle.project_poly(X32.astype(np.float64), "fp32", lam=lam)
+    assert rel_fro(out, ref) < 1e-5
+
+
+def test_batched_equals_single():
+    import torch
+    sizes = [40, 129, 300]
+    Xs = [to_dev(inputs.goe(n, 70 + n)) for n in sizes]
+    outs = P.project_batched(Xs, mode="bf16")
+    singles = [P.project(X, mode="bf16") for X in Xs]
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        assert torch.equal(a, b)
