@@ -131,6 +131,13 @@ int psdproj_release(void);
 
 const char *psdproj_status_string(int status);
 
+/* Tuning hook (process-wide, not thread-safe against concurrent launches):
+ * "gemm_tile" = 0 (automatic), 128 or 256 forces the GEMM tile edge where it
+ * divides the padded size; "gemm_block" = H * 256 + W sets the blocking of
+ * the GEMM tile schedule (H tile rows x W tile columns per block).
+ * Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
+int psdproj_tune(const char *key, int64_t value);
+
 /* ---- kernel-level entry points (used by tests and tooling) ---------------
  * psdproj_sym_gemm: D = alpha C0 + beta (L R) + gamma I on n_p x n_p
  * symmetric work matrices (column-major, leading dimension ld >= n_p,

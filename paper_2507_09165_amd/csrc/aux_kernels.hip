@@ -288,82 +288,133 @@ __global__ __launch_bounds__(256) void lz_next_kernel(double *V, int64_t n, int 
     if (stop && blockIdx.x == 0 && threadIdx.x == 0) scal->stop = 1;
 }
 
-// Largest eigenpair of the k x k tridiagonal T (alpha, beta): bisection on the
-// Sturm count for sigma, then inverse iteration with a dense partially pivoted
-// LU for the eigenvector s (k <= 32, one thread).
-__global__ void lz_ritz_kernel(Scalars *scal) {
-    if (threadIdx.x != 0) return;
-    const int k = scal->k;
-    const double *al = scal->alpha, *be = scal->beta;
-    double lo = 0.0, hi = 0.0;
-    for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
-        lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
-        hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
-    }
-    const double scale_t = fmax(fabs(lo), fabs(hi));
-    const double tiny = 1e-300 + 1e-30 * scale_t;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        int cnt = 0;  // number of eigenvalues < mid
-        double d = al[0] - mid;
+// Number of eigenvalues of the k x k symmetric tridiagonal (al, be) below x
+// (Sylvester inertia of the LDL^T factorisation of T - x I).
+__device__ __forceinline__ int sturm_count(const double *al, const double *be, int k, double x, double tiny) {
+    int cnt = 0;
+    double d = al[0] - x;
+    if (d == 0.0) d = -tiny;
+    cnt += d < 0.0;
+    for (int i = 1; i < k; ++i) {
+        d = al[i] - x - be[i - 1] * be[i - 1] / d;
         if (d == 0.0) d = -tiny;
         cnt += d < 0.0;
-        for (int i = 1; i < k; ++i) {
-            d = al[i] - mid - be[i - 1] * be[i - 1] / d;
-            if (d == 0.0) d = -tiny;
-            cnt += d < 0.0;
-        }
-        if (cnt == k) hi = mid; else lo = mid;
     }
+    return cnt;
+}
+
+// Largest eigenpair of the k x k tridiagonal T (alpha, beta) of the Lanczos
+// run (k <= KM). sigma: multisection of the Gershgorin interval on the Sturm
+// count, one wave evaluating 64 shifts per round. s: inverse iteration on
+// T - sigma I with a partially pivoted tridiagonal LU (one thread; loops are
+// unrolled to KM with guards so the arrays stay in registers).
+template <int KM>
+__global__ __launch_bounds__(64) void lz_ritz_kernel(Scalars *scal) {
+    const int lane = threadIdx.x;
+    const int k = scal->k;
+    __shared__ double al[kMaxLanczos], be[kMaxLanczos];
+    __shared__ double lo_hi[2];
+    if (lane < kMaxLanczos) {
+        al[lane] = lane < k ? scal->alpha[lane] : 0.0;
+        be[lane] = lane < k - 1 ? scal->beta[lane] : 0.0;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double lo = 0.0, hi = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
+            lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
+            hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
+        }
+        lo_hi[0] = lo;
+        lo_hi[1] = hi;
+    }
+    __syncthreads();
+    double lo = lo_hi[0], hi = lo_hi[1];
+    const double scale_t = fmax(fabs(lo), fabs(hi));
+    const double tiny = 1e-300 + 1e-30 * scale_t;
+    // invariant: count(lo) < k (sigma >= lo), count(hi) == k (sigma < hi)
+    hi = hi + 1e-15 * scale_t + tiny;
+    for (int it = 0; it < 40; ++it) {
+        if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi))) || !(hi > lo)) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const int all_below = sturm_count(al, be, k, x, tiny) == k;
+        const unsigned long long m = __ballot(all_below);  // lanes whose shift is above sigma
+        const int f = m ? __ffsll((long long)m) - 1 : 64;
+        const double nlo = f == 0 ? lo : lo + (hi - lo) * (double)f / 65.0;
+        const double nhi = f == 64 ? hi : lo + (hi - lo) * (double)(f + 1) / 65.0;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane != 0) return;
     const double sigma = 0.5 * (lo + hi);
     scal->sigma = sigma;
-    // inverse iteration on (T - sigma I)
-    double M[kMaxLanczos][kMaxLanczos];
-    int piv[kMaxLanczos];
-    for (int r = 0; r < k; ++r)
-        for (int c = 0; c < k; ++c) M[r][c] = 0.0;
-    for (int r = 0; r < k; ++r) {
-        M[r][r] = al[r] - sigma;
-        if (r + 1 < k) M[r][r + 1] = M[r + 1][r] = be[r];
+    // LU of T - sigma I with partial pivoting: rows i, i+1 may swap; U has two
+    // superdiagonals (du, du2); dl holds the multipliers.
+    double d[KM], du[KM], du2[KM], dl[KM], x[KM];
+    bool sw[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+        d[i] = i < k ? al[i] - sigma : 1.0;
+        du[i] = i < k - 1 ? be[i] : 0.0;
+        dl[i] = i < k - 1 ? be[i] : 0.0;
+        du2[i] = 0.0;
+        sw[i] = false;
+        x[i] = i < k ? 1.0 : 0.0;
     }
     const double eps_p = 1e-15 * (scale_t > 0.0 ? scale_t : 1.0);
-    for (int c = 0; c < k; ++c) {
-        int p = c;
-        for (int r = c + 1; r < k; ++r)
-            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
-        piv[c] = p;
-        if (p != c)
-            for (int q = 0; q < k; ++q) {
-                const double tmp = M[c][q]; M[c][q] = M[p][q]; M[p][q] = tmp;
+#pragma unroll
+    for (int i = 0; i < KM - 1; ++i) {
+        if (i < k - 1) {
+            if (fabs(d[i]) >= fabs(dl[i])) {
+                if (fabs(d[i]) < eps_p) d[i] = d[i] < 0.0 ? -eps_p : eps_p;
+                const double f = dl[i] / d[i];
+                dl[i] = f;
+                d[i + 1] -= f * du[i];
+            } else {
+                const double f = d[i] / dl[i];
+                d[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t - f * d[i + 1];
+                if (i < k - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                sw[i] = true;
             }
-        if (fabs(M[c][c]) < eps_p) M[c][c] = (M[c][c] < 0.0 ? -eps_p : eps_p);
-        for (int r = c + 1; r < k; ++r) {
-            const double f = M[r][c] / M[c][c];
-            M[r][c] = f;
-            for (int q = c + 1; q < k; ++q) M[r][q] -= f * M[c][q];
         }
     }
-    double x[kMaxLanczos];
-    for (int i = 0; i < k; ++i) x[i] = 1.0;
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+        if (i == k - 1 && fabs(d[i]) < eps_p) d[i] = d[i] < 0.0 ? -eps_p : eps_p;
     for (int it = 0; it < 3; ++it) {
-        for (int c = 0; c < k; ++c) {  // apply the row swaps and L^-1
-            const int p = piv[c];
-            if (p != c) { const double tmp = x[c]; x[c] = x[p]; x[p] = tmp; }
-            for (int r = c + 1; r < k; ++r) x[r] -= M[r][c] * x[c];
+#pragma unroll
+        for (int i = 0; i < KM - 1; ++i) {  // L^-1 P
+            if (i < k - 1) {
+                if (sw[i]) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
+                x[i + 1] -= dl[i] * x[i];
+            }
         }
-        for (int r = k - 1; r >= 0; --r) {  // U^-1
-            double s = x[r];
-            for (int q = r + 1; q < k; ++q) s -= M[r][q] * x[q];
-            x[r] = s / M[r][r];
+#pragma unroll
+        for (int i = KM - 1; i >= 0; --i) {  // U^-1
+            if (i < k) {
+                double v = x[i];
+                if (i + 1 < KM && i + 1 < k) v -= du[i] * x[i + 1];
+                if (i + 2 < KM && i + 2 < k) v -= du2[i] * x[i + 2];
+                x[i] = v / d[i];
+            }
         }
         double nrm = 0.0;
-        for (int i = 0; i < k; ++i) nrm += x[i] * x[i];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) nrm += i < k ? x[i] * x[i] : 0.0;
         nrm = sqrt(nrm);
-        for (int i = 0; i < k; ++i) x[i] = nrm > 0.0 ? x[i] / nrm : (i == 0 ? 1.0 : 0.0);
+#pragma unroll
+        for (int i = 0; i < KM; ++i) x[i] = i < k ? (nrm > 0.0 ? x[i] / nrm : (i == 0 ? 1.0 : 0.0)) : 0.0;
     }
-    for (int i = 0; i < kMaxLanczos; ++i) scal->s[i] = i < k ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxLanczos; ++i) scal->s[i] = i < KM ? x[i < KM ? i : 0] * (i < k ? 1.0 : 0.0) : 0.0;
 }
 
 // q = V[:, 0..k) s; part <- ||q||^2
@@ -476,7 +527,10 @@ hipError_t spectral_bound(const float *Xf, int64_t ldx, int64_t n, int steps, ui
         hipLaunchKernelGGL(lz_next_kernel, dim3(nbv), dim3(256), 0, s, V, n, j, steps, (const double *)w,
                            (const double *)pa, scal);
     }
-    hipLaunchKernelGGL(lz_ritz_kernel, dim3(1), dim3(64), 0, s, scal);
+    if (steps <= 20)
+        hipLaunchKernelGGL(lz_ritz_kernel<20>, dim3(1), dim3(64), 0, s, scal);
+    else
+        hipLaunchKernelGGL(lz_ritz_kernel<kMaxLanczos>, dim3(1), dim3(64), 0, s, scal);
     hipLaunchKernelGGL(lz_q_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, u, pa, (const Scalars *)scal);
     hipLaunchKernelGGL(lz_qnorm_kernel, dim3(1), dim3(64), 0, s, (const double *)pa, (int)nbv, scal);
     hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)u,

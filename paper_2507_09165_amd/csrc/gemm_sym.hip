@@ -22,6 +22,12 @@
 // accumulates L_hi (S R_hi) + L_hi R_lo + L_lo R_hi into one FP32 accumulator
 // (R_hi is scaled by S in registers, exact for |R| < 32) and the epilogue
 // multiplies by 1/S.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "common.hpp"
 #include "gemm_sym.hpp"
 
@@ -62,158 +68,201 @@ __device__ __forceinline__ u32x4 scale_frag(u32x4 v, float) { return v; }
 template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
 template <typename T> __device__ __forceinline__ T from_f(float v) { return (T)v; }
 
-// Upper-triangle tile index -> (bi, bj), tiles enumerated column by column:
-// t = bj (bj + 1) / 2 + bi, 0 <= bi <= bj.
-__device__ __forceinline__ void tri_tile(int t, int &bi, int &bj) {
-    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    while ((j + 1) * (j + 2) / 2 <= t) ++j;
-    while (j * (j + 1) / 2 > t) --j;
-    bj = j;
-    bi = t - j * (j + 1) / 2;
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give every XCD one contiguous run of the column-ordered tile list, so
+// the tiles resident on one XCD share operand panels. Bijective for any count.
+__device__ __forceinline__ int xcd_remap(int w, int count) {
+    const int xcd = w & 7, idx = w >> 3;
+    const int per = count >> 3, rem = count & 7;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-constexpr int kRowBytes = 128;  // one K-tile per LDS row: 8 chunks of 16 bytes
-constexpr int kThreads = 256;   // 4 waves in a 2 x 2 layout
+constexpr int kThreads = 256;  // 4 waves in a 2 x 2 layout
 
-template <typename T, bool LS, bool RS, int EPI, int BM>
+typedef __attribute__((address_space(1))) void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+
+// 16-byte chunk c of LDS row r is stored at chunk position swz(r, c). The
+// fragment reads of one ds_read_b128 take rows r..r+31 at one logical chunk;
+// gfx950 serves 16 lanes per cycle from 64 banks, so any 16 consecutive rows
+// (and any 8) must land on distinct 16-byte bank groups. XOR with a key that
+// changes with both r and r / 8 does that for 128-byte and 64-byte rows.
+template <int NCH>
+__device__ __forceinline__ int swz(int r, int c) {
+    if constexpr (NCH == 8) return c ^ ((r + (r >> 3)) & 7);
+    else return c ^ (((r >> 1) + (r >> 3)) & 3);
+}
+
+template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
-    constexpr int BN = BM;
+    constexpr int NCH = ROWB / 16;            // 16-byte chunks per LDS row
+    constexpr int NSUB = NCH / 2;             // MFMA K-substeps per row
     constexpr int NLP = LS ? 2 : 1;
     constexpr int NRP = RS ? 2 : 1;
-    constexpr int PANEL_L = BM * kRowBytes;
-    constexpr int PANEL_R = BN * kRowBytes;
-    constexpr int STAGE = NLP * PANEL_L + NRP * PANEL_R;
-    constexpr int BK = kRowBytes / (int)sizeof(T);
-    constexpr int CPT_L = BM * 8 / kThreads;  // 16-byte chunks per thread per panel
-    constexpr int CPT_R = BN * 8 / kThreads;
-    constexpr int WM = BM / 2, WN = BN / 2;   // wave tile
-    constexpr int MI = WM / 32, NI = WN / 32;
+    constexpr int PANEL = BM * ROWB;
+    constexpr int STAGE = (NLP + NRP) * PANEL;
+    constexpr int BK = ROWB / (int)sizeof(T);
+    constexpr int CPT = BM * NCH / kThreads;  // chunks per thread per panel
+    constexpr int WM = BM / 2;                // wave tile edge
+    constexpr int MI = WM / 32;
+    static_assert(BM * NCH % kThreads == 0 && WM % 32 == 0, "tile shape");
     __shared__ __attribute__((aligned(16))) uint8_t smem[2 * STAGE];
 
-    int bi, bj;
-    tri_tile(blockIdx.x, bi, bj);
+    const uint32_t tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int bi = (int)(tv & 0xFFFFu), bj = (int)(tv >> 16);
     const int64_t i0 = (int64_t)bi * BM;
-    const int64_t j0 = (int64_t)bj * BN;
+    const int64_t j0 = (int64_t)bj * BM;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = (wave >> 1) * WM;
-    const int wc = (wave & 1) * WN;
+    const int wc = (wave & 1) * WM;
     const int64_t ld = g.ld;
 
-    const uint8_t *Lsrc[2] = {(const uint8_t *)g.Lhi, (const uint8_t *)g.Llo};
-    const uint8_t *Rsrc[2] = {(const uint8_t *)g.Rhi, (const uint8_t *)g.Rlo};
-
-    u32x4 pf[NLP * CPT_L + NRP * CPT_R];
-
-    auto gload = [&](int64_t kt) {
-        const int64_t kb = kt * BK * (int64_t)sizeof(T);
+    // Operand panels of one K-tile, in LDS order: L_hi, [L_lo], R_hi, [R_lo].
+    const uint8_t *src[4];
+    {
+        int p = 0;
+        src[p++] = (const uint8_t *)g.Lhi;
+        if constexpr (LS) src[p++] = (const uint8_t *)g.Llo;
+        src[p++] = (const uint8_t *)g.Rhi;
+        if constexpr (RS) src[p++] = (const uint8_t *)g.Rlo;
+    }
+    // Direct global->LDS loads: one wave instruction moves 64 x 16 bytes into
+    // 1 KB of contiguous LDS (lane l -> byte 16 l). The K-tile of all panels
+    // is NLD such kilobytes per wave; lane l of load j fills LDS row r at
+    // physical chunk pc, so it fetches logical chunk swz(r, pc) of that row.
+    constexpr int NLD = (NLP + NRP) * PANEL / (1024 * 4);
+    constexpr int RPL = 1024 / ROWB;  // LDS rows per wave load
+    static_assert((NLP + NRP) * PANEL % 4096 == 0, "panel split over waves");
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const uint8_t *gsrc[NLD];
 #pragma unroll
-        for (int p = 0; p < NLP; ++p)
+    for (int j = 0; j < NLD; ++j) {
+        const int kb = (wave * NLD + j) * 1024;  // byte offset in the stage
+        const int p = kb / PANEL;
+        const int r = (kb % PANEL) / ROWB + lane / NCH;
+        const int pc = lane % NCH;
+        const int64_t row = (p < NLP ? i0 : j0) + r;
+        gsrc[j] = src[p] + row * ld * (int64_t)sizeof(T) + (swz<NCH>(r, pc) << 4);
+    }
+    auto issue_loads = [&](int64_t kt, int buf) {
+        const int64_t kb = kt * ROWB;
+        uint8_t *dst = smem + buf * STAGE + wave_u * NLD * 1024;
 #pragma unroll
-            for (int s = 0; s < CPT_L; ++s) {
-                const int q = tid + kThreads * s, r = q >> 3, c = q & 7;
-                const uint8_t *src = Lsrc[p] + ((i0 + r) * ld) * (int64_t)sizeof(T) + kb + c * 16;
-                pf[p * CPT_L + s] = *(const u32x4 *)src;
-            }
-#pragma unroll
-        for (int p = 0; p < NRP; ++p)
-#pragma unroll
-            for (int s = 0; s < CPT_R; ++s) {
-                const int q = tid + kThreads * s, r = q >> 3, c = q & 7;
-                const uint8_t *src = Rsrc[p] + ((j0 + r) * ld) * (int64_t)sizeof(T) + kb + c * 16;
-                pf[NLP * CPT_L + p * CPT_R + s] = *(const u32x4 *)src;
-            }
+        for (int j = 0; j < NLD; ++j)
+            __builtin_amdgcn_global_load_lds((gptr_t)(gsrc[j] + kb), (lptr_t)(dst + j * 1024), 16, 0, 0);
     };
-    auto sstore = [&](int buf) {
-        uint8_t *base = smem + buf * STAGE;
-#pragma unroll
-        for (int p = 0; p < NLP; ++p)
-#pragma unroll
-            for (int s = 0; s < CPT_L; ++s) {
-                const int q = tid + kThreads * s, r = q >> 3, c = q & 7;
-                *(u32x4 *)(base + p * PANEL_L + r * kRowBytes + ((c ^ (r & 7)) << 4)) = pf[p * CPT_L + s];
-            }
-#pragma unroll
-        for (int p = 0; p < NRP; ++p)
-#pragma unroll
-            for (int s = 0; s < CPT_R; ++s) {
-                const int q = tid + kThreads * s, r = q >> 3, c = q & 7;
-                *(u32x4 *)(base + NLP * PANEL_L + p * PANEL_R + r * kRowBytes + ((c ^ (r & 7)) << 4)) =
-                    pf[NLP * CPT_L + p * CPT_R + s];
-            }
-    };
+    static_assert(RPL * NCH == 64, "lane layout");
 
-    f32x16 acc[MI][NI];
+    f32x16 acc[MI][MI];
 #pragma unroll
     for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < NI; ++ni)
+        for (int ni = 0; ni < MI; ++ni)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[mi][ni][e] = 0.0f;
 
+    // fragment row offsets inside a panel, and the row's swizzle key
+    int roff_a[MI], roff_b[MI], key_a[MI], key_b[MI];
+#pragma unroll
+    for (int m = 0; m < MI; ++m) {
+        const int ra = wr + m * 32 + (lane & 31), rb = wc + m * 32 + (lane & 31);
+        roff_a[m] = ra * ROWB;
+        roff_b[m] = rb * ROWB;
+        key_a[m] = swz<NCH>(ra, 0);
+        key_b[m] = swz<NCH>(rb, 0);
+    }
+
     const int64_t nk = g.K / BK;
-    gload(0);
-    sstore(0);
+    // Fragments of one K-substep: operand panel p, MFMA block m.
+    typedef u32x4 Frag[NLP + NRP][MI];
+    auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
+        const int cl = 2 * sub + (lane >> 5);
+#pragma unroll
+        for (int p = 0; p < NLP; ++p)
+#pragma unroll
+            for (int m = 0; m < MI; ++m)
+                f[p][m] = *(const u32x4 *)(base + p * PANEL + roff_a[m] + ((cl ^ key_a[m]) << 4));
+#pragma unroll
+        for (int p = 0; p < NRP; ++p)
+#pragma unroll
+            for (int m = 0; m < MI; ++m)
+                f[NLP + p][m] = *(const u32x4 *)(base + (NLP + p) * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
+    };
+    auto mfmas = [&](const Frag &f) {
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < MI; ++ni) {
+                if constexpr (LS || RS) {
+                    mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
+                    if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
+                    if constexpr (LS) mma(acc[mi][ni], f[1][mi], f[NLP][ni], T{});
+                } else {
+                    mma(acc[mi][ni], f[0][mi], f[NLP][ni], T{});
+                }
+            }
+    };
+    constexpr int NMF = MI * MI * (1 + (LS ? 1 : 0) + (RS ? 1 : 0));  // MFMAs per substep
+    constexpr int NDS = (NLP + NRP) * MI;                            // ds_reads per substep
+    Frag fr[2];
+    issue_loads(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    load_frags(smem, 0, fr[0]);
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int buf = (int)(kt & 1);
-        if (kt + 1 < nk) gload(kt + 1);
         const uint8_t *base = smem + buf * STAGE;
+        // The other buffer was last read in iteration kt - 1, which every
+        // wave finished before the barrier that ended it. On the last
+        // iteration the (unused) final tile is fetched again.
+        issue_loads(kt + 1 < nk ? kt + 1 : kt, buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub) {
-            const int cl = 2 * sub + (lane >> 5);
-            u32x4 a[NLP][MI], b[NRP][NI];
-#pragma unroll
-            for (int p = 0; p < NLP; ++p)
-#pragma unroll
-                for (int mi = 0; mi < MI; ++mi) {
-                    const int r = wr + mi * 32 + (lane & 31);
-                    a[p][mi] = *(const u32x4 *)(base + p * PANEL_L + r * kRowBytes + ((cl ^ (r & 7)) << 4));
-                }
-#pragma unroll
-            for (int p = 0; p < NRP; ++p)
-#pragma unroll
-                for (int ni = 0; ni < NI; ++ni) {
-                    const int r = wc + ni * 32 + (lane & 31);
-                    b[p][ni] = *(const u32x4 *)(base + NLP * PANEL_L + p * PANEL_R + r * kRowBytes + ((cl ^ (r & 7)) << 4));
-                }
-#pragma unroll
-            for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < NI; ++ni) {
-                    if constexpr (LS || RS) {
-                        mma(acc[mi][ni], a[0][mi], scale_frag(b[0][ni], T{}), T{});
-                        if constexpr (RS) mma(acc[mi][ni], a[0][mi], b[NRP - 1][ni], T{});
-                        if constexpr (LS) mma(acc[mi][ni], a[NLP - 1][mi], b[0][ni], T{});
-                    } else {
-                        mma(acc[mi][ni], a[0][mi], b[0][ni], T{});
-                    }
-                }
+        for (int sub = 0; sub < NSUB; ++sub) {
+            // next substep's fragments first, then this substep's MFMAs on
+            // fragments loaded one substep earlier: the reads overlap the
+            // MFMAs and the waits only cover the older reads
+            if (sub + 1 < NSUB) load_frags(base, sub + 1, fr[(sub + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(fr[sub & 1]);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if (kt + 1 < nk) sstore(buf ^ 1);
+        // own direct-to-LDS loads landed, then all waves' loads and reads
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        load_frags(smem + (buf ^ 1) * STAGE, 0, fr[0]);
     }
 
     // ---------------- epilogue ----------------
+    // Accumulator layout of a 32x32 MFMA block: lane l, register e holds
+    // row 8 (e / 4) + 4 (l / 32) + (e % 4), column l % 32.
     const float acc_scale = (LS || RS) ? 1.0f / Elt<T>::kSplit : 1.0f;
     const bool diag = (bi == bj);
     if constexpr (EPI == EPI_FINAL) {
         if (g.scal->nonfinite) return;  // leave the output untouched
-        const float lam = (float)g.scal->lam;
+        const float hl = 0.5f * (float)g.scal->lam * acc_scale;
         const int64_t n = g.n;
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < NI; ++ni)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int64_t i = i0 + wr + mi * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+#pragma clang loop unroll(full)
+            for (int ni = 0; ni < MI; ++ni)
+#pragma clang loop unroll(full)
+                for (int eg = 0; eg < 4; ++eg) {
+                    const int64_t ib = i0 + wr + mi * 32 + 8 * eg + 4 * (lane >> 5);
                     const int64_t j = j0 + wc + ni * 32 + (lane & 31);
-                    if (i >= n || j >= n || (diag && i > j)) continue;
-                    const float v = 0.5f * g.Xf[i * g.ldxf + j] + 0.5f * lam * (acc[mi][ni][e] * acc_scale);
-                    g.out[i * g.ldo + j] = v;
-                    g.out[j * g.ldo + i] = v;
+                    if (j >= n || ib >= n) continue;
+                    const float4 x4 = *(const float4 *)(g.Xf + j * g.ldxf + ib);
+                    const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma clang loop unroll(full)
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t i = ib + q;
+                        if (i >= n || (diag && i > j)) continue;
+                        const float v = 0.5f * xv[q] + hl * acc[mi][ni][4 * eg + q];
+                        g.out[j * g.ldo + i] = v;
+                        g.out[i * g.ldo + j] = v;
+                    }
                 }
     } else {
         T *Dhi = (T *)g.Dhi;
@@ -221,43 +270,132 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const T *C0hi = (const T *)g.C0hi;
         const T *C0lo = (const T *)g.C0lo;
         const float c0lo = 1.0f / Elt<T>::kSplit;
-#pragma unroll
+        typedef T t4 __attribute__((ext_vector_type(4)));
+#pragma clang loop unroll(full)
         for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < NI; ++ni)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int64_t i = i0 + wr + mi * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+#pragma clang loop unroll(full)
+            for (int ni = 0; ni < MI; ++ni)
+#pragma clang loop unroll(full)
+                for (int eg = 0; eg < 4; ++eg) {
+                    const int64_t ib = i0 + wr + mi * 32 + 8 * eg + 4 * (lane >> 5);
                     const int64_t j = j0 + wc + ni * 32 + (lane & 31);
-                    if (diag && i > j) continue;
-                    float v = g.beta * (acc[mi][ni][e] * acc_scale);
+                    float v[4];
+#pragma clang loop unroll(full)
+                    for (int q = 0; q < 4; ++q) v[q] = g.beta * (acc[mi][ni][4 * eg + q] * acc_scale);
                     if (C0hi) {
-                        float c0 = to_f(C0hi[i * ld + j]);
-                        if (C0lo) c0 += to_f(C0lo[i * ld + j]) * c0lo;
-                        v += g.alpha * c0;
+                        const t4 c = *(const t4 *)(C0hi + j * ld + ib);
+#pragma clang loop unroll(full)
+                        for (int q = 0; q < 4; ++q) v[q] += g.alpha * to_f(c[q]);
+                        if (C0lo) {
+                            const t4 cl = *(const t4 *)(C0lo + j * ld + ib);
+#pragma clang loop unroll(full)
+                            for (int q = 0; q < 4; ++q) v[q] += g.alpha * (to_f(cl[q]) * c0lo);
+                        }
                     }
-                    if (i == j) v += g.gamma;
-                    const T hi = from_f<T>(v);
-                    Dhi[i * ld + j] = hi;
-                    Dhi[j * ld + i] = hi;
-                    if constexpr (EPI == EPI_STORE_SPLIT) {
-                        const T lo = from_f<T>((v - to_f(hi)) * Elt<T>::kSplit);
-                        Dlo[i * ld + j] = lo;
-                        Dlo[j * ld + i] = lo;
+                    t4 hi, lo;
+#pragma clang loop unroll(full)
+                    for (int q = 0; q < 4; ++q) {
+                        if (ib + q == j) v[q] += g.gamma;
+                        hi[q] = from_f<T>(v[q]);
+                        lo[q] = from_f<T>((v[q] - to_f(hi[q])) * Elt<T>::kSplit);
+                    }
+                    if (!diag) {
+                        *(t4 *)(Dhi + j * ld + ib) = hi;
+                        if constexpr (EPI == EPI_STORE_SPLIT) *(t4 *)(Dlo + j * ld + ib) = lo;
+#pragma clang loop unroll(full)
+                        for (int q = 0; q < 4; ++q) {
+                            Dhi[(ib + q) * ld + j] = hi[q];
+                            if constexpr (EPI == EPI_STORE_SPLIT) Dlo[(ib + q) * ld + j] = lo[q];
+                        }
+                    } else {
+#pragma clang loop unroll(full)
+                        for (int q = 0; q < 4; ++q) {
+                            const int64_t i = ib + q;
+                            if (i > j) continue;
+                            Dhi[j * ld + i] = hi[q];
+                            Dhi[i * ld + j] = hi[q];
+                            if constexpr (EPI == EPI_STORE_SPLIT) {
+                                Dlo[j * ld + i] = lo[q];
+                                Dlo[i * ld + j] = lo[q];
+                            }
+                        }
                     }
                 }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, bool LS, bool RS, int EPI>
-static hipError_t launch_t(const GemmArgs &g, hipStream_t s) {
-    constexpr int BM = kTile;
+// Tile schedule. The upper-triangle tiles are listed in blocks of H tile rows
+// x W tile columns (super-rows of height H, walked left to right in chunks of
+// W columns). The launch gives each XCD a contiguous run of this list, so the
+// ~32 tiles resident on one XCD at a time form a compact 2D block that shares
+// H + W operand panels in its L2 instead of one panel per tile.
+static int g_tile_override = 0;  // tuning hook: force a tile edge (0 = automatic)
+static int g_block_h = 4, g_block_w = 8;
+
+std::vector<uint32_t> make_tile_order(int T, int H, int W) {
+    std::vector<uint32_t> v;
+    v.reserve((size_t)T * (T + 1) / 2);
+    for (int s0 = 0; s0 < T; s0 += H)
+        for (int c0 = s0; c0 < T; c0 += W)
+            for (int bj = c0; bj < std::min(c0 + W, T); ++bj)
+                for (int bi = s0; bi < std::min(s0 + H, T); ++bi)
+                    if (bi <= bj) v.push_back((uint32_t)bi | ((uint32_t)bj << 16));
+    return v;
+}
+
+static std::mutex g_tiles_mu;
+static std::map<std::tuple<int, int, int, int, int>, uint32_t *> g_tiles;
+
+// Device copy of the tile list for (device, T, H, W); built once (the first
+// use synchronises the device for the upload).
+static const uint32_t *tile_list(int T, hipError_t *err) {
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    const auto key = std::make_tuple(dev, T, g_block_h, g_block_w, 0);
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    auto it = g_tiles.find(key);
+    if (it != g_tiles.end()) return it->second;
+    const std::vector<uint32_t> v = make_tile_order(T, g_block_h, g_block_w);
+    uint32_t *d = nullptr;
+    *err = hipMalloc(&d, v.size() * sizeof(uint32_t));
+    if (*err != hipSuccess) return nullptr;
+    *err = hipMemcpy(d, v.data(), v.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (*err != hipSuccess) { (void)hipFree(d); return nullptr; }
+    g_tiles[key] = d;
+    return d;
+}
+
+int gemm_pick_tile(int64_t K) {
+    if (g_tile_override && K % g_tile_override == 0) return g_tile_override;
+    if (K % 256 == 0 && K >= 2048) return 256;
+    return 128;
+}
+
+template <typename T, bool LS, bool RS, int EPI, int BM>
+static hipError_t launch_bm(const GemmArgs &g, hipStream_t s) {
+    constexpr int NP = 2 + (LS ? 1 : 0) + (RS ? 1 : 0);
+    // LDS row width: keep two stages within 160 KB
+    constexpr int ROWB = (2 * NP * BM * 128 <= 160 * 1024) ? 128 : 64;
     const int T_ = (int)(g.K / BM);
     const int ntiles = T_ * (T_ + 1) / 2;
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM>), dim3(ntiles), dim3(kThreads), 0, s, g);
+    hipError_t err;
+    GemmArgs a = g;
+    a.tiles = tile_list(T_, &err);
+    if (!a.tiles) return err;
+    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB>), dim3(ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
+}
+
+template <typename T, bool LS, bool RS, int EPI>
+static hipError_t launch_t(const GemmArgs &g, hipStream_t s) {
+    switch (gemm_pick_tile(g.K)) {
+        case 256: return launch_bm<T, LS, RS, EPI, 256>(g, s);
+        case 128: return launch_bm<T, LS, RS, EPI, 128>(g, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int EPI>
@@ -290,6 +428,13 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, hipStream_t s)
         case DT_BF16: return launch_epi<bf16>(g, epi, s);
     }
     return hipErrorInvalidValue;
+}
+
+void gemm_set_tile_override(int bm) { g_tile_override = bm; }
+void gemm_set_block_shape(int h, int w) {
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    g_block_h = h;
+    g_block_w = w;
 }
 
 }  // namespace psd

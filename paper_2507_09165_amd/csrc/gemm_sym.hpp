@@ -24,11 +24,23 @@ struct GemmArgs {
     const float *Xf;
     int64_t ldxf;
     const Scalars *scal;
+    const uint32_t *tiles;  // filled by the launcher: tile list (bi | bj << 16)
     int64_t ld;  // leading dimension of the work matrices
     int64_t K;   // padded size n_p (multiple of kTile)
     float alpha, beta, gamma;  // D = alpha C0 + beta (L R) + gamma I
 };
 
 hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, hipStream_t s);
+
+// Tile edge the launcher uses for a padded size K, and the padded size used for
+// a logical size n (a multiple of the tile it will run with).
+int gemm_pick_tile(int64_t K);
+inline int64_t gemm_padded_size(int64_t n) {
+    return n >= 1536 ? round_up(n, 256) : round_up(n > 0 ? n : 1, kTile);
+}
+// Tuning hook: force the tile edge (0 restores the automatic choice).
+void gemm_set_tile_override(int bm);
+// Tuning hook: blocking of the tile schedule (H tile rows x W tile columns).
+void gemm_set_block_shape(int h, int w);
 
 }  // namespace psd

@@ -72,7 +72,7 @@ struct Layout {
 Layout make_layout(int64_t n, const StagePlan &p, int steps) {
     Layout L{};
     L.n = n;
-    L.np = round_up(n > 0 ? n : 1, kTile);
+    L.np = gemm_padded_size(n);
     L.ldxf = round_up(n > 0 ? n : 1, 64);
     L.steps = steps;
     L.split = p.split_mask != 0 || p.split_final;
@@ -337,6 +337,22 @@ int psdproj_release(void) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     g_pool.clear();
     return PSDPROJ_OK;
+}
+
+int psdproj_tune(const char *key, int64_t value) {
+    if (!key) return PSDPROJ_ERR_INVALID_ARG;
+    if (!strcmp(key, "gemm_tile")) {
+        if (value != 0 && value != 128 && value != 256) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_tile_override((int)value);
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "gemm_block")) {  // value = H * 256 + W
+        const int h = (int)(value >> 8), w = (int)(value & 255);
+        if (h < 1 || w < 1 || h > 64 || w > 64) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_block_shape(h, w);
+        return PSDPROJ_OK;
+    }
+    return PSDPROJ_ERR_NOT_FOUND;
 }
 
 const char *psdproj_status_string(int status) {

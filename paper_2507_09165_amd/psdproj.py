@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
     L.psdproj_release.argtypes = []
     L.psdproj_status_string.argtypes = [c_int]
     L.psdproj_status_string.restype = ctypes.c_char_p
+    L.psdproj_tune.argtypes = [ctypes.c_char_p, i64]
+    L.psdproj_tune.restype = c_int
     L.psdproj_sym_gemm.argtypes = [c_int, i64, i64, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     for name in ("psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
@@ -193,6 +195,10 @@ def coefficients(mode="fp16") -> np.ndarray:
     if T < 0:
         raise PsdprojError(1, "psdproj_coefficients")
     return np.array(buf[: 3 * T]).reshape(T, 3)
+
+
+def tune(key: str, value: int):
+    _check(lib().psdproj_tune(key.encode(), int(value)), f"psdproj_tune({key})")
 
 
 def release():
