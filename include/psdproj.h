@@ -138,6 +138,72 @@ const char *psdproj_status_string(int status);
  * Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
 int psdproj_tune(const char *key, int64_t value);
 
+/* ---- serving: a continuous-batching request loop -------------------------
+ * A server owns `slots` HIP streams (default priority) and a scheduler thread.
+ * Requests are admitted in arrival order as soon as a slot is free and the
+ * workspace the request needs fits under hbm_budget_bytes together with the
+ * workspaces already held by the slots (later, smaller requests may pass a
+ * blocked head request at most `max_bypass` times). Admitted work runs on the
+ * slot's stream, so requests that arrive while others are on the GPU overlap
+ * with them. Iterates stay in caller-owned HBM: X and out are device pointers
+ * that must stay valid until the request completes. Results of a request do
+ * not depend on the mix it runs in (tile shapes are a function of (n, mode)
+ * only). Timestamps are host CLOCK_MONOTONIC nanoseconds; a request's latency
+ * is end_ns - submit_ns, where end_ns is when the scheduler observed the
+ * completion event. */
+typedef struct psdproj_server psdproj_server;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* 0 -> 200 GB */
+    int slots;               /* concurrent streams, 0 -> 4 */
+    int max_bypass;          /* 0 -> 8 */
+    int fake_executor;       /* 1: no GPU work; a request "runs" for a modelled
+                                time (tests of the scheduling logic on a CPU) */
+    double fake_tflops;      /* fake executor speed (0 -> 500) */
+} psdproj_serve_config;
+
+typedef struct {
+    int64_t n, ld;
+    const float *X;  /* device, upper triangle read */
+    float *out;      /* device */
+    double target;   /* accuracy target when mode < 0: <= 1e-4 -> FP32,
+                        otherwise FP16_SPLIT */
+    int mode;        /* psdproj_mode, or -1 to choose from target */
+    uint64_t tag;    /* caller's tag, echoed in the result */
+} psdproj_request;
+
+typedef struct {
+    int status;      /* PSDPROJ_OK, _REJECTED, _CANCELLED, _HIP, ... */
+    int mode;
+    uint64_t tag;
+    int64_t submit_ns, start_ns, end_ns;
+    int slot;
+} psdproj_result;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled, pending, running;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests */
+    double throughput_per_s;                /* completed / (last end - first submit) */
+    size_t bytes_held, peak_bytes_held;     /* workspace held by the slots */
+} psdproj_serve_statistics;
+
+/* Create a server on the current device. NULL config -> defaults. */
+int psdproj_serve_create(const psdproj_serve_config *cfg, psdproj_server **out);
+/* Queue a request; *ticket identifies it. A request whose workspace alone
+ * exceeds the budget is rejected (PSDPROJ_ERR_REJECTED, no ticket issued). */
+int psdproj_serve_submit(psdproj_server *s, const psdproj_request *r, uint64_t *ticket);
+/* Wait up to timeout_ns (< 0: forever) for a request; PSDPROJ_ERR_TIMEOUT if
+ * it has not finished, PSDPROJ_ERR_NOT_FOUND for an unknown ticket. The
+ * result is returned (and forgotten) once finished. */
+int psdproj_serve_wait(psdproj_server *s, uint64_t ticket, int64_t timeout_ns, psdproj_result *res);
+/* Non-blocking: PSDPROJ_ERR_PENDING while queued or running. */
+int psdproj_serve_poll(psdproj_server *s, uint64_t ticket, psdproj_result *res);
+/* Cancel a request that has not started (PSDPROJ_ERR_PENDING if it is running). */
+int psdproj_serve_cancel(psdproj_server *s, uint64_t ticket);
+int psdproj_serve_stats(psdproj_server *s, psdproj_serve_statistics *st);
+/* Drain running work, cancel queued requests, free streams and workspaces. */
+int psdproj_serve_destroy(psdproj_server *s);
+
 /* ---- kernel-level entry points (used by tests and tooling) ---------------
  * psdproj_sym_gemm: D = alpha C0 + beta (L R) + gamma I on n_p x n_p
  * symmetric work matrices (column-major, leading dimension ld >= n_p,

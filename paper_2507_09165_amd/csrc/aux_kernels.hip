@@ -114,73 +114,90 @@ __device__ __forceinline__ double start_entry(uint64_t i, uint64_t seed) {
     return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
 }
 
-constexpr int kMvCols = 4;    // output entries per wave
-constexpr int kMvWaves = 4;   // waves per block
+// ---------------------------------------------------------------------------
+// Symmetric matvec from the upper triangle. The triangle is cut into
+// kTB x kTB tiles (I <= J, enumerated column by column: t = J (J + 1) / 2 + I).
+// Tile (I, J) reads its upper part once and produces
+//   d[t][c] = sum_{i in I} X(i, j0 + c) v_i           (column dots)
+//   a[t][r] = sum_{j in J} X(i0 + r, j) v_j           (row sums, i < j only)
+// and y_k = sum_{I <= K} d[tile(I, K)][k] + sum_{J >= K} a[tile(K, J)][k],
+// summed in that fixed order by symv_reduce_kernel. With NORMS the same is
+// done for X(i, j)^2 and v = 1, which yields the full column norms.
+// ---------------------------------------------------------------------------
+constexpr int kTB = 128;
 
-// y[i] = scale * sum_j X(j, i) v[j] for the symmetric Xf (column i == row i).
-// Optionally colsq[i] = sum_j X(j, i)^2. Skips all work once the breakdown
-// flag is set (stop_on_flag).
-__global__ __launch_bounds__(256) void matvec_kernel(const float *__restrict__ Xf, int64_t ldx, int64_t n,
-                                                     const double *__restrict__ v, const double *vscale,
-                                                     double *__restrict__ y, double *__restrict__ colsq,
-                                                     const Scalars *scal, int stop_on_flag) {
+__device__ __forceinline__ void tile_of(int t, int &I, int &J) {
+    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    while (j * (j + 1) / 2 > t) --j;
+    J = j;
+    I = t - j * (j + 1) / 2;
+}
+
+template <bool NORMS>
+__global__ __launch_bounds__(256) void symv_tile_kernel(const float *__restrict__ X, int64_t ld, int64_t n,
+                                                        const double *__restrict__ v, const double *vscale,
+                                                        double *__restrict__ d, double *__restrict__ a,
+                                                        double *__restrict__ d2, double *__restrict__ a2,
+                                                        const Scalars *scal, int stop_on_flag) {
     if (stop_on_flag && scal->stop) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t c0 = ((int64_t)blockIdx.x * kMvWaves + wave) * kMvCols;
-    double acc[kMvCols], sq[kMvCols];
-#pragma unroll
-    for (int c = 0; c < kMvCols; ++c) acc[c] = sq[c] = 0.0;
-    const bool vec4 = ((ldx & 3) == 0);
-    if (vec4) {
-        const int64_t n4 = n & ~(int64_t)3;
-        for (int64_t k = (int64_t)lane * 4; k < n4; k += 256) {
-            const double v0 = v[k], v1 = v[k + 1], v2 = v[k + 2], v3 = v[k + 3];
-#pragma unroll
-            for (int c = 0; c < kMvCols; ++c) {
-                const int64_t col = c0 + c;
-                if (col < n) {
-                    const float4 x = *(const float4 *)(Xf + col * ldx + k);
-                    acc[c] += (double)x.x * v0 + (double)x.y * v1 + (double)x.z * v2 + (double)x.w * v3;
-                    if (colsq) sq[c] += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
-                }
-            }
-        }
-        for (int64_t k = n4 + lane; k < n; k += 64) {
-            const double vk = v[k];
-#pragma unroll
-            for (int c = 0; c < kMvCols; ++c) {
-                const int64_t col = c0 + c;
-                if (col < n) {
-                    const double x = Xf[col * ldx + k];
-                    acc[c] += x * vk;
-                    if (colsq) sq[c] += x * x;
-                }
-            }
-        }
+    const int t = blockIdx.x;
+    int I, J;
+    tile_of(t, I, J);
+    const int64_t i0 = (int64_t)I * kTB, j0 = (int64_t)J * kTB;
+    const bool diag = (I == J);
+    __shared__ double vI[kTB], vJ[kTB];
+    __shared__ double red[4][kTB], red2[4][kTB];
+    const double sc = vscale ? *vscale : 1.0;
+    if (threadIdx.x < kTB) {
+        const int64_t i = i0 + threadIdx.x;
+        vI[threadIdx.x] = i < n ? v[i] * sc : 0.0;
     } else {
-        for (int64_t k = lane; k < n; k += 64) {
-            const double vk = v[k];
-#pragma unroll
-            for (int c = 0; c < kMvCols; ++c) {
-                const int64_t col = c0 + c;
-                if (col < n) {
-                    const double x = Xf[col * ldx + k];
-                    acc[c] += x * vk;
-                    if (colsq) sq[c] += x * x;
-                }
-            }
+        const int64_t j = j0 + threadIdx.x - kTB;
+        vJ[threadIdx.x - kTB] = j < n ? v[j] * sc : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = 2 * lane;  // this lane's two rows of the tile
+    const int64_t ia = i0 + r0, ib = ia + 1;
+    double ax0 = 0.0, ax1 = 0.0, sq0 = 0.0, sq1 = 0.0;
+    const double via = vI[r0], vib = vI[r0 + 1];
+    // wave w handles tile columns c = 32 w .. 32 w + 31
+#pragma unroll 8
+    for (int cc = 0; cc < 32; ++cc) {
+        const int c = 32 * wave + cc;
+        const int64_t j = j0 + c;
+        float x0 = 0.0f, x1 = 0.0f;
+        if (j < n) {
+            const float *col = X + j * ld;
+            if (ia < n && (!diag || ia <= j)) x0 = col[ia];
+            if (ib < n && (!diag || ib <= j)) x1 = col[ib];
+        }
+        const double dot = wave_sum((double)x0 * via + (double)x1 * vib);
+        const double vj = vJ[c];
+        // row sums: strictly upper entries only (the diagonal is in the dot)
+        const bool u0 = !diag || ia < j, u1 = !diag || ib < j;
+        ax0 += u0 ? (double)x0 * vj : 0.0;
+        ax1 += u1 ? (double)x1 * vj : 0.0;
+        if (lane == 0) d[(int64_t)t * kTB + c] = dot;
+        if constexpr (NORMS) {
+            const double q = wave_sum((double)x0 * x0 + (double)x1 * x1);
+            sq0 += u0 ? (double)x0 * x0 : 0.0;
+            sq1 += u1 ? (double)x1 * x1 : 0.0;
+            if (lane == 0) d2[(int64_t)t * kTB + c] = q;
         }
     }
-    const double sc = vscale ? *vscale : 1.0;
-#pragma unroll
-    for (int c = 0; c < kMvCols; ++c) {
-        const double a = wave_sum(acc[c]);
-        const double q = colsq ? wave_sum(sq[c]) : 0.0;
-        const int64_t col = c0 + c;
-        if (lane == 0 && col < n) {
-            y[col] = a * sc;
-            if (colsq) colsq[col] = q;
-        }
+    red[wave][r0] = ax0;
+    red[wave][r0 + 1] = ax1;
+    if constexpr (NORMS) {
+        red2[wave][r0] = sq0;
+        red2[wave][r0 + 1] = sq1;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTB) {
+        const int r = threadIdx.x;
+        a[(int64_t)t * kTB + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
+        if constexpr (NORMS) a2[(int64_t)t * kTB + r] = red2[0][r] + red2[1][r] + red2[2][r] + red2[3][r];
     }
 }
 
@@ -206,6 +223,47 @@ __device__ __forceinline__ double sum_partials(const double *part, int nb, int s
     double s = 0.0;
     for (int b = 0; b < nb; ++b) s += part[(int64_t)b * stride + k];
     return s;
+}
+
+// y_k from the symv tile partials (fixed order: column dots of tiles I <= K,
+// then row sums of tiles J >= K). NORMS: also colsq_k. ORTH0: also the first
+// Gram-Schmidt partials part[block][c] = sum over this block's rows of
+// V[i, c] y_i, c <= jstep (the block covers kRows rows).
+template <bool NORMS, bool ORTH0>
+__global__ __launch_bounds__(256) void symv_reduce_kernel(int64_t n, const double *__restrict__ d,
+                                                          const double *__restrict__ a, const double *__restrict__ d2,
+                                                          const double *__restrict__ a2, double *__restrict__ y,
+                                                          double *__restrict__ colsq, const double *__restrict__ V,
+                                                          int jstep, double *__restrict__ part, const Scalars *scal,
+                                                          int stop_on_flag) {
+    if (stop_on_flag && scal->stop) return;
+    const int64_t k = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    const int T = (int)((n + kTB - 1) / kTB);
+    double yk = 0.0, ck = 0.0;
+    if (k < n) {
+        const int K = (int)(k / kTB), kk = (int)(k % kTB);
+        const int64_t base = (int64_t)K * (K + 1) / 2;
+        for (int I = 0; I <= K; ++I) {
+            yk += d[(base + I) * kTB + kk];
+            if constexpr (NORMS) ck += d2[(base + I) * kTB + kk];
+        }
+        for (int J = K; J < T; ++J) {
+            const int64_t t = (int64_t)J * (J + 1) / 2 + K;
+            yk += a[t * kTB + kk];
+            if constexpr (NORMS) ck += a2[t * kTB + kk];
+        }
+        y[k] = yk;
+        if constexpr (NORMS) colsq[k] = ck;
+    }
+    if constexpr (ORTH0) {
+        __shared__ double red[4 * kMaxLanczos];
+        double h[kMaxLanczos];
+#pragma unroll
+        for (int c = 0; c < kMaxLanczos; ++c) h[c] = (c <= jstep && k < n) ? V[(int64_t)c * n + k] * yk : 0.0;
+        block_reduce<kMaxLanczos>(h, red);
+        if (threadIdx.x == 0)
+            for (int c = 0; c <= jstep; ++c) part[(int64_t)blockIdx.x * kMaxLanczos + c] = h[c];
+    }
 }
 
 // Start vector: V[:, 0] = v / ||v||. Pass 0 writes v and the partial norms,
@@ -503,23 +561,44 @@ __global__ void scal_init_kernel(Scalars *scal) {
     }
 }
 
-hipError_t spectral_bound(const float *Xf, int64_t ldx, int64_t n, int steps, uint64_t seed, LanczosWork wk,
+hipError_t spectral_bound(const float *X, int64_t ldx, int64_t n, int steps, uint64_t seed, LanczosWork wk,
                           Scalars *scal, int force_fallback, hipStream_t s) {
     if (steps < 1 || steps > kMaxLanczos) return hipErrorInvalidValue;
     const unsigned nbv = (unsigned)((n + kRows - 1) / kRows);
-    const unsigned nbm = (unsigned)((n + kMvCols * kMvWaves - 1) / (kMvCols * kMvWaves));
+    const int64_t T = (n + kTB - 1) / kTB;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
     if (nbv == 0) return hipSuccess;
     double *V = wk.V, *u = wk.u, *w = wk.w, *pa = wk.part_a, *pb = wk.part_b;
+    double *d = wk.sd, *a = wk.sa, *d2 = wk.sd2, *a2 = wk.sa2;
+    const double *nulld = nullptr;
+    // y = X v: tile partials, then the fixed-order reduction (+ first GS pass)
+    auto symv = [&](const double *vin, const double *vscale, double *yout, bool norms, bool orth0, int jstep,
+                    double *part, int stop_flag) {
+        if (norms) {
+            hipLaunchKernelGGL(symv_tile_kernel<true>, dim3(ntiles), dim3(256), 0, s, X, ldx, n, vin, vscale, d, a,
+                               d2, a2, (const Scalars *)scal, stop_flag);
+            hipLaunchKernelGGL((symv_reduce_kernel<true, false>), dim3(nbv), dim3(256), 0, s, n, (const double *)d,
+                               (const double *)a, (const double *)d2, (const double *)a2, yout, wk.colsq, nulld, 0,
+                               (double *)nullptr, (const Scalars *)scal, stop_flag);
+        } else {
+            hipLaunchKernelGGL(symv_tile_kernel<false>, dim3(ntiles), dim3(256), 0, s, X, ldx, n, vin, vscale, d, a,
+                               (double *)nullptr, (double *)nullptr, (const Scalars *)scal, stop_flag);
+            if (orth0)
+                hipLaunchKernelGGL((symv_reduce_kernel<false, true>), dim3(nbv), dim3(256), 0, s, n,
+                                   (const double *)d, (const double *)a, nulld, nulld, yout, (double *)nullptr,
+                                   (const double *)V, jstep, part, (const Scalars *)scal, stop_flag);
+            else
+                hipLaunchKernelGGL((symv_reduce_kernel<false, false>), dim3(nbv), dim3(256), 0, s, n,
+                                   (const double *)d, (const double *)a, nulld, nulld, yout, (double *)nullptr, nulld,
+                                   0, (double *)nullptr, (const Scalars *)scal, stop_flag);
+        }
+    };
     hipLaunchKernelGGL(scal_init_kernel, dim3(1), dim3(64), 0, s, scal);
     hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 0, seed);
     hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 1, seed);
     for (int j = 0; j < steps; ++j) {
-        hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, V + (int64_t)j * n,
-                           (const double *)nullptr, u, j == 0 ? wk.colsq : (double *)nullptr, scal, 1);
-        hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)u,
-                           (const double *)nullptr, w, (double *)nullptr, scal, 1);
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w,
-                           (const double *)nullptr, pa, scal, 0);
+        symv(V + (int64_t)j * n, nullptr, u, j == 0, false, 0, nullptr, 1);  // u = X v_j
+        symv(u, nullptr, w, false, true, j, pa, 1);                           // w = X u, part_a = V^T w
         hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pa,
                            pb, scal, 1);
         hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pb,
@@ -533,10 +612,8 @@ hipError_t spectral_bound(const float *Xf, int64_t ldx, int64_t n, int steps, ui
         hipLaunchKernelGGL(lz_ritz_kernel<kMaxLanczos>, dim3(1), dim3(64), 0, s, scal);
     hipLaunchKernelGGL(lz_q_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, u, pa, (const Scalars *)scal);
     hipLaunchKernelGGL(lz_qnorm_kernel, dim3(1), dim3(64), 0, s, (const double *)pa, (int)nbv, scal);
-    hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)u,
-                       (const double *)&scal->qnorm_inv, w, (double *)nullptr, scal, 0);
-    hipLaunchKernelGGL(matvec_kernel, dim3(nbm), dim3(256), 0, s, Xf, ldx, n, (const double *)w,
-                       (const double *)nullptr, wk.w2, (double *)nullptr, scal, 0);
+    symv(u, &scal->qnorm_inv, w, false, false, 0, nullptr, 0);  // X q_hat
+    symv(w, nullptr, wk.w2, false, false, 0, nullptr, 0);       // X^2 q_hat
     hipLaunchKernelGGL(lz_resid_kernel, dim3(nbv), dim3(256), 0, s, (const double *)wk.w2, (const double *)u, n, pa,
                        (const Scalars *)scal);
     hipLaunchKernelGGL(lz_bound_kernel, dim3(1), dim3(256), 0, s, (const double *)wk.colsq, n, (const double *)pa,
@@ -546,7 +623,14 @@ hipError_t spectral_bound(const float *Xf, int64_t ldx, int64_t n, int steps, ui
 
 size_t lanczos_work_doubles(int64_t n, int steps) {
     const int64_t nbv = (n + kRows - 1) / kRows;
-    return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + 64);
+    const int64_t T = (n + kTB - 1) / kTB;
+    const int64_t tiles = T * (T + 1) / 2;
+    return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + 4 * tiles * kTB + 64);
+}
+
+int64_t symv_tile_count(int64_t n) {
+    const int64_t T = (n + kTB - 1) / kTB;
+    return T * (T + 1) / 2;
 }
 
 }  // namespace psd

@@ -90,10 +90,18 @@ typedef __attribute__((address_space(3))) void *lptr_t;
 template <int NCH>
 __device__ __forceinline__ int swz(int r, int c) {
     if constexpr (NCH == 8) return c ^ ((r + (r >> 3)) & 7);
-    else return c ^ (((r >> 1) + (r >> 3)) & 3);
+    else if constexpr (NCH == 4) return c ^ (((r >> 1) + (r >> 3)) & 3);
+    else return c ^ (((r >> 2) ^ (r >> 3)) & 1);
 }
 
-template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB>
+// vmcnt-only wait (expcnt and lgkmcnt left unconstrained), gfx9 encoding.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int NCH = ROWB / 16;            // 16-byte chunks per LDS row
     constexpr int NSUB = NCH / 2;             // MFMA K-substeps per row
@@ -106,7 +114,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int WM = BM / 2;                // wave tile edge
     constexpr int MI = WM / 32;
     static_assert(BM * NCH % kThreads == 0 && WM % 32 == 0, "tile shape");
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * STAGE];
+    static_assert(NST >= 2, "at least two LDS stages");
+    __shared__ __attribute__((aligned(16))) uint8_t smem[NST * STAGE];
 
     const uint32_t tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const int bi = (int)(tv & 0xFFFFu), bj = (int)(tv >> 16);
@@ -207,33 +216,40 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int NMF = MI * MI * (1 + (LS ? 1 : 0) + (RS ? 1 : 0));  // MFMAs per substep
     constexpr int NDS = (NLP + NRP) * MI;                            // ds_reads per substep
     Frag fr[2];
-    issue_loads(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
+    // Every wave issues exactly NLD loads per iteration (the index is clamped
+    // at the end), so "tile kt+1 has landed" is vmcnt <= NLD * (NST - 2).
+#pragma unroll
+    for (int t = 0; t < NST - 1; ++t) issue_loads(t < nk ? t : nk - 1, t);
+    wait_vmcnt<NLD * (NST - 2)>();
+    __builtin_amdgcn_s_barrier();
     load_frags(smem, 0, fr[0]);
     for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = (int)(kt & 1);
-        const uint8_t *base = smem + buf * STAGE;
-        // The other buffer was last read in iteration kt - 1, which every
-        // wave finished before the barrier that ended it. On the last
-        // iteration the (unused) final tile is fetched again.
-        issue_loads(kt + 1 < nk ? kt + 1 : kt, buf ^ 1);
+        const int st = (int)(kt % NST);
+        const uint8_t *base = smem + st * STAGE;
+        // stage (kt - 1) mod NST was last read in iteration kt - 1, which every
+        // wave finished before the barrier that ended it
+        const int64_t tn = kt + NST - 1;
+        issue_loads(tn < nk ? tn : nk - 1, (int)((kt + NST - 1) % NST));
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
             // next substep's fragments first, then this substep's MFMAs on
-            // fragments loaded one substep earlier: the reads overlap the
-            // MFMAs and the waits only cover the older reads
+            // fragments loaded one substep earlier
             if (sub + 1 < NSUB) load_frags(base, sub + 1, fr[(sub + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
             mfmas(fr[sub & 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // own direct-to-LDS loads landed, then all waves' loads and reads
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        load_frags(smem + (buf ^ 1) * STAGE, 0, fr[0]);
+        // Tile kt + 1 landed for this wave, then (barrier) for all waves. A
+        // plain s_barrier: a fenced __syncthreads would wait for every
+        // outstanding load (vmcnt(0)) and undo the prefetch. Every ds_read of
+        // the stage about to be refilled was consumed by an MFMA above.
+        wait_vmcnt<NLD * (NST - 2)>();
+        __builtin_amdgcn_s_barrier();
+        load_frags(smem + (int)((kt + 1) % NST) * STAGE, 0, fr[0]);
     }
+    __builtin_amdgcn_s_waitcnt(0);
 
     // ---------------- epilogue ----------------
     // Accumulator layout of a 32x32 MFMA block: lane l, register e holds
@@ -253,13 +269,13 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                     const int64_t ib = i0 + wr + mi * 32 + 8 * eg + 4 * (lane >> 5);
                     const int64_t j = j0 + wc + ni * 32 + (lane & 31);
                     if (j >= n || ib >= n) continue;
-                    const float4 x4 = *(const float4 *)(g.Xf + j * g.ldxf + ib);
-                    const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma clang loop unroll(full)
                     for (int q = 0; q < 4; ++q) {
                         const int64_t i = ib + q;
                         if (i >= n || (diag && i > j)) continue;
-                        const float v = 0.5f * xv[q] + hl * acc[mi][ni][4 * eg + q];
+                        // upper-triangle entry (i <= j): read then written by
+                        // this thread only, so out == X is safe
+                        const float v = 0.5f * g.Xin[j * g.ldx + i] + hl * acc[mi][ni][4 * eg + q];
                         g.out[j * g.ldo + i] = v;
                         g.out[i * g.ldo + j] = v;
                     }
@@ -373,11 +389,20 @@ int gemm_pick_tile(int64_t K) {
     return 128;
 }
 
+// LDS configuration per (tile, operand panels): the 128 tile keeps two
+// 128-byte stages (64 KB, two workgroups per CU); the 256 tile uses a 4-stage
+// ring within 128 KB with rows as wide as that allows.
+template <int BM, int NP> struct LdsCfg {
+    static constexpr int NST = BM == 256 ? 4 : 2;
+    static constexpr int ROWB_MAX = (128 * 1024) / (NST * NP * BM);
+    static constexpr int ROWB = ROWB_MAX >= 128 ? 128 : ROWB_MAX >= 64 ? 64 : 32;
+};
+
 template <typename T, bool LS, bool RS, int EPI, int BM>
 static hipError_t launch_bm(const GemmArgs &g, hipStream_t s) {
     constexpr int NP = 2 + (LS ? 1 : 0) + (RS ? 1 : 0);
-    // LDS row width: keep two stages within 160 KB
-    constexpr int ROWB = (2 * NP * BM * 128 <= 160 * 1024) ? 128 : 64;
+    constexpr int ROWB = LdsCfg<BM, NP>::ROWB;
+    constexpr int NST = LdsCfg<BM, NP>::NST;
     const int T_ = (int)(g.K / BM);
     const int ntiles = T_ * (T_ + 1) / 2;
     if (ntiles == 0) return hipSuccess;
@@ -385,7 +410,7 @@ static hipError_t launch_bm(const GemmArgs &g, hipStream_t s) {
     GemmArgs a = g;
     a.tiles = tile_list(T_, &err);
     if (!a.tiles) return err;
-    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB>), dim3(ntiles), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST>), dim3(ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

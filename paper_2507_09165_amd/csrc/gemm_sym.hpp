@@ -17,12 +17,13 @@ struct GemmArgs {
     // Epilogue addend C0 (same layout; may be nullptr) and outputs.
     const void *C0hi, *C0lo;
     void *Dhi, *Dlo;
-    // Final epilogue: out (FP32, n x n, ldo) = (Xf + lam * acc) / 2.
+    // Final epilogue: out (FP32, n x n, ldo) = (X + lam * acc) / 2, X read from
+    // its upper triangle (Xin, column-major, leading dimension ldx).
     float *out;
     int64_t ldo;
     int64_t n;
-    const float *Xf;
-    int64_t ldxf;
+    const float *Xin;
+    int64_t ldx;
     const Scalars *scal;
     const uint32_t *tiles;  // filled by the launcher: tile list (bi | bj << 16)
     int64_t ld;  // leading dimension of the work matrices

@@ -13,6 +13,7 @@
 #include "coeffs.hpp"
 #include "common.hpp"
 #include "gemm_sym.hpp"
+#include "runtime.hpp"
 
 namespace psd {
 namespace {
@@ -63,23 +64,21 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
 struct Layout {
-    int64_t n, np, ldxf;
+    int64_t n, np;
     int steps;
     bool split;
-    size_t off_scal, off_xf, off_lz, off_mat, mat_bytes, total;
+    size_t off_scal, off_lz, off_mat, mat_bytes, total;
 };
 
 Layout make_layout(int64_t n, const StagePlan &p, int steps) {
     Layout L{};
     L.n = n;
     L.np = gemm_padded_size(n);
-    L.ldxf = round_up(n > 0 ? n : 1, 64);
     L.steps = steps;
     L.split = p.split_mask != 0 || p.split_final;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += round_up((int64_t)bytes, 256); return o; };
     L.off_scal = take(sizeof(Scalars));
-    L.off_xf = take(sizeof(float) * (size_t)L.ldxf * (size_t)L.ldxf);
     L.off_lz = take(sizeof(double) * lanczos_work_doubles(n, steps));
     L.mat_bytes = round_up((int64_t)(elt_size(p.dtype) * (size_t)L.np * (size_t)L.np), 256);
     L.off_mat = take(L.mat_bytes * 4 * (L.split ? 2 : 1));
@@ -144,6 +143,8 @@ struct Mat {
     void *hi = nullptr, *lo = nullptr;
 };
 
+}  // namespace
+
 int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
                    psdproj_info *info, bool bound_only) {
     StagePlan p;
@@ -161,11 +162,11 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     if (st != PSDPROJ_OK) return st;
     uint8_t *b = (uint8_t *)base;
     Scalars *scal = (Scalars *)(b + L.off_scal);
-    float *Xf = (float *)(b + L.off_xf);
     double *lz = (double *)(b + L.off_lz);
     LanczosWork wk;
     {
         const int64_t nbv = (n + 255) / 256;
+        const int64_t tiles = symv_tile_count(n);
         wk.V = lz;
         wk.u = wk.V + n * steps;
         wk.w = wk.u + n;
@@ -173,13 +174,14 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
         wk.colsq = wk.w2 + n;
         wk.part_a = wk.colsq + n;
         wk.part_b = wk.part_a + nbv * kMaxLanczos;
+        wk.sd = wk.part_b + nbv * kMaxLanczos;
+        wk.sa = wk.sd + tiles * 128;
+        wk.sd2 = wk.sa + tiles * 128;
+        wk.sa2 = wk.sd2 + tiles * 128;
     }
     hipError_t e;
-    // 1. full symmetric FP32 copy of the upper triangle (read by the Lanczos matvecs)
-    e = mirror_cast(X, ld, n, L.ldxf, scal, 0, DT_F32, Xf, nullptr, L.ldxf, s);
-    if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-    // 2. spectral bound (Theorem 2) + guard
-    e = spectral_bound(Xf, L.ldxf, n, steps, kLanczosSeed, wk, scal, o.force_bound_fallback, s);
+    // 1-2. spectral bound (Theorem 2) + guard, from the upper triangle of X
+    e = spectral_bound(X, ld, n, steps, kLanczosSeed, wk, scal, o.force_bound_fallback, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (o.lambda_override > 0.0) hipLaunchKernelGGL(override_kernel, dim3(1), dim3(64), 0, s, scal, o.lambda_override);
     if (bound_only) {
@@ -237,7 +239,7 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     g.Rhi = slot[cur].hi; g.Rlo = p.split_final ? slot[cur].lo : nullptr;
     g.C0hi = g.C0lo = nullptr;
     g.Dhi = g.Dlo = nullptr;
-    g.out = out; g.ldo = ld; g.n = n; g.Xf = Xf; g.ldxf = L.ldxf;
+    g.out = out; g.ldo = ld; g.n = n; g.Xin = X; g.ldx = ld;
     e = gemm_sym_launch(g, p.dtype, EPI_FINAL, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, (const Scalars *)scal, info, p.T);
@@ -252,7 +254,52 @@ psdproj_opts default_opts(int mode) {
     return o;
 }
 
-}  // namespace
+size_t workspace_bytes_for(int64_t n, int mode) {
+    psdproj_opts o = default_opts(mode);
+    StagePlan p;
+    if (n <= 0 || !make_stage_plan(o, p)) return 0;
+    return make_layout(n, p, kDefaultLanczos).total;
+}
+
+size_t pool_held(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_pool.find({dev, s});
+    return it == g_pool.end() ? 0 : it->second.bytes;
+}
+
+void pool_release(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_pool.find({dev, s});
+    if (it == g_pool.end()) return;
+    if (it->second.ptr) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(it->second.ptr);
+    }
+    g_pool.erase(it);
+}
+
+int gemm_count_for(const psdproj_opts &o) {
+    StagePlan p;
+    if (!make_stage_plan(o, p)) return -1;
+    int g = 0;
+    bool cur_split = (p.split_mask & 1u) != 0;
+    for (int t = 0; t < p.T; ++t) {
+        const bool sp = (p.split_mask >> t) & 1u;
+        const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
+        const bool xs = sp && cur_split;
+        g += xs ? 3 : 1;      // X X
+        g += sp ? 3 : 1;      // A A
+        g += sp ? (xs ? 3 : 2) : 1;  // X B
+        cur_split = next_split;
+    }
+    g += p.split_final ? 3 : 1;
+    return g;
+}
+
 }  // namespace psd
 
 using namespace psd;
@@ -292,31 +339,13 @@ int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld, cons
     return PSDPROJ_OK;
 }
 
-size_t psdproj_workspace_bytes(int64_t n, int mode) {
-    psdproj_opts o = default_opts(mode);
-    StagePlan p;
-    if (n <= 0 || !make_stage_plan(o, p)) return 0;
-    return make_layout(n, p, kDefaultLanczos).total;
-}
+size_t psdproj_workspace_bytes(int64_t n, int mode) { return workspace_bytes_for(n, mode); }
 
 int psdproj_gemm_count(const psdproj_opts *opts, int mode) {
     psdproj_opts o = opts ? *opts : default_opts(mode);
-    StagePlan p;
-    if (!make_stage_plan(o, p)) return -1;
-    int g = 0;
-    bool cur_split = (p.split_mask & 1u) != 0;
-    for (int t = 0; t < p.T; ++t) {
-        const bool sp = (p.split_mask >> t) & 1u;
-        const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
-        const bool xs = sp && cur_split;
-        g += xs ? 3 : 1;      // X X
-        g += sp ? 3 : 1;      // A A
-        g += sp ? (xs ? 3 : 2) : 1;  // X B
-        cur_split = next_split;
-    }
-    g += p.split_final ? 3 : 1;
-    return g;
+    return gemm_count_for(o);
 }
+
 
 int psdproj_coefficients(int mode, double *abc, int cap) {
     psdproj_opts o = default_opts(mode);

@@ -1,0 +1,23 @@
+// Internal runtime interface shared by the C ABI and the serving loop.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/psdproj.h"
+#include "common.hpp"
+
+namespace psd {
+
+// Enqueue one projection (or only the bound) on stream s.
+int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
+                   psdproj_info *info, bool bound_only);
+psdproj_opts default_opts(int mode);
+// Workspace bytes a projection of size n in mode needs (0 for a bad mode).
+size_t workspace_bytes_for(int64_t n, int mode);
+// Number of n_p x n_p products the projection runs.
+int gemm_count_for(const psdproj_opts &o);
+// Per-(device, stream) workspace pool: bytes currently held, and release.
+size_t pool_held(hipStream_t s);
+void pool_release(hipStream_t s);
+
+}  // namespace psd

@@ -1,0 +1,407 @@
+// Continuous-batching request loop for PSD projections (psdproj_serve_*).
+//
+// One scheduler thread owns `slots` HIP streams. Each request needs the
+// workspace of one projection; each slot keeps its own workspace pool, grown
+// to the largest request it has served. Admission (in arrival order) takes a
+// free slot whose pool can host the request without the slots' total
+// exceeding the HBM budget; a blocked head request may be passed by later
+// ones at most max_bypass times. Work is enqueued on the slot's stream and a
+// completion event is recorded; the scheduler polls the events, stamps the
+// result and wakes waiters. Requests that arrive while others run are
+// admitted as slots free up, so their kernels overlap on the device.
+//
+// The fake executor (config.fake_executor) runs no GPU work: a request
+// "completes" after a modelled time, so the admission and bookkeeping logic
+// can be exercised on a machine without a GPU.
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/psdproj.h"
+#include "runtime.hpp"
+
+namespace {
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
+
+struct Req {
+    psdproj_request r;
+    int mode = 0;
+    size_t ws = 0;
+    int64_t submit_ns = 0, start_ns = 0, end_ns = 0;
+    int status = PSDPROJ_ERR_PENDING;
+    int slot = -1;
+    int bypassed = 0;
+    bool finished = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    uint64_t ticket = 0;
+    size_t held = 0;        // workspace bytes this slot's pool holds
+    int64_t fake_end = 0;
+};
+
+}  // namespace
+
+struct psdproj_server {
+    psdproj_serve_config cfg{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, Req> reqs;
+    std::vector<Slot> slots;
+    std::thread th;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    // statistics
+    std::vector<double> lat_ms;
+    uint64_t n_sub = 0, n_done = 0, n_rej = 0, n_cancel = 0;
+    int64_t first_submit = 0, last_end = 0;
+    size_t peak_held = 0;
+
+    size_t held_total() const {
+        size_t s = 0;
+        for (const Slot &sl : slots) s += sl.held;
+        return s;
+    }
+    int running() const {
+        int c = 0;
+        for (const Slot &sl : slots) c += sl.busy;
+        return c;
+    }
+    void loop();
+    int pick_slot(size_t ws);
+    void launch(int si, uint64_t ticket, std::unique_lock<std::mutex> &lk);
+    void poll_completions();
+};
+
+static int choose_mode(const psdproj_request &r) {
+    if (r.mode >= 0) return r.mode;
+    return r.target <= 1e-4 ? PSDPROJ_MODE_FP32 : PSDPROJ_MODE_FP16_SPLIT;
+}
+
+// Pick a free slot for a request of `ws` bytes: prefer the smallest pool that
+// already fits, else the largest pool whose growth keeps the budget. If no
+// slot qualifies but idle slots hold pools, release idle pools (largest
+// first) until one can grow. Returns -1 if the request must wait.
+int psdproj_server::pick_slot(size_t ws) {
+    const size_t total = held_total();
+    int best = -1;
+    for (int i = 0; i < (int)slots.size(); ++i) {
+        const Slot &sl = slots[i];
+        if (sl.busy) continue;
+        if (sl.held >= ws) {
+            if (best < 0 || slots[best].held < ws || sl.held < slots[best].held) best = i;
+        } else if (total - sl.held + ws <= cfg.hbm_budget_bytes) {
+            if (best < 0 || (slots[best].held < ws && sl.held > slots[best].held)) best = i;
+        }
+    }
+    if (best >= 0) return best;
+    std::vector<int> idle;
+    for (int i = 0; i < (int)slots.size(); ++i)
+        if (!slots[i].busy) idle.push_back(i);
+    if (idle.empty()) return -1;
+    std::sort(idle.begin(), idle.end(), [&](int a, int b) { return slots[a].held > slots[b].held; });
+    const int cand = idle[0];
+    size_t t = total;
+    for (size_t k = 1; k < idle.size() && t - slots[cand].held + ws > cfg.hbm_budget_bytes; ++k) {
+        Slot &sl = slots[idle[k]];
+        if (!sl.held) continue;
+        if (!cfg.fake_executor) psd::pool_release(sl.stream);  // stream is idle
+        t -= sl.held;
+        sl.held = 0;
+    }
+    return t - slots[cand].held + ws <= cfg.hbm_budget_bytes ? cand : -1;
+}
+
+void psdproj_server::launch(int si, uint64_t ticket, std::unique_lock<std::mutex> &lk) {
+    Slot &sl = slots[si];
+    Req &q = reqs[ticket];
+    sl.busy = true;
+    sl.ticket = ticket;
+    q.slot = si;
+    q.start_ns = now_ns();
+    if (cfg.fake_executor) {
+        const psdproj_opts o = psd::default_opts(q.mode);
+        const double n = (double)q.r.n;
+        const double flops = (double)psd::gemm_count_for(o) * n * n * (n + 1.0);
+        sl.fake_end = q.start_ns + 30000 + (int64_t)(flops / (cfg.fake_tflops * 1e12) * 1e9);
+        sl.held = std::max(sl.held, q.ws);
+    } else {
+        const psdproj_request r = q.r;
+        const int mode = q.mode;
+        hipStream_t st = sl.stream;
+        hipEvent_t ev = sl.done;
+        lk.unlock();  // enqueueing ~160 launches takes a while; let clients submit
+        const psdproj_opts o = psd::default_opts(mode);
+        int status = psd::run_projection(o, r.n, r.ld, r.X, r.out, st, nullptr, false);
+        if (status == PSDPROJ_OK && hipEventRecord(ev, st) != hipSuccess) status = PSDPROJ_ERR_HIP;
+        const size_t held = psd::pool_held(st);
+        lk.lock();
+        Req &q2 = reqs[ticket];
+        slots[si].held = held;
+        if (status != PSDPROJ_OK) {  // nothing left in flight for this request
+            q2.status = status;
+            q2.end_ns = now_ns();
+            q2.finished = true;
+            slots[si].busy = false;
+            cv_done.notify_all();
+        }
+    }
+    peak_held = std::max(peak_held, held_total());
+}
+
+void psdproj_server::poll_completions() {
+    const int64_t t = now_ns();
+    for (int i = 0; i < (int)slots.size(); ++i) {
+        Slot &sl = slots[i];
+        if (!sl.busy) continue;
+        int status = PSDPROJ_OK;
+        if (cfg.fake_executor) {
+            if (t < sl.fake_end) continue;
+        } else {
+            const hipError_t e = hipEventQuery(sl.done);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) status = PSDPROJ_ERR_HIP;
+        }
+        Req &q = reqs[sl.ticket];
+        q.end_ns = now_ns();
+        q.status = status;
+        q.finished = true;
+        sl.busy = false;
+        if (status == PSDPROJ_OK) {
+            ++n_done;
+            lat_ms.push_back((q.end_ns - q.submit_ns) * 1e-6);
+            last_end = std::max(last_end, q.end_ns);
+        }
+        cv_done.notify_all();
+    }
+}
+
+void psdproj_server::loop() {
+    if (!cfg.fake_executor) (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        poll_completions();
+        // Admissions in arrival order; a blocked head may be passed by later
+        // requests at most max_bypass times. launch() drops the lock while it
+        // enqueues, so the queue is rescanned after every admission.
+        bool admitted = true;
+        while (admitted && !pending.empty()) {
+            admitted = false;
+            for (size_t idx = 0; idx < pending.size(); ++idx) {
+                const uint64_t tk = pending[idx];
+                const int si = pick_slot(reqs[tk].ws);
+                if (si >= 0) {
+                    pending.erase(pending.begin() + (long)idx);
+                    if (idx > 0) ++reqs[pending.front()].bypassed;
+                    launch(si, tk, lk);
+                    admitted = true;
+                    break;
+                }
+                if (idx == 0 && reqs[tk].bypassed >= cfg.max_bypass) break;
+            }
+        }
+        if (stop && pending.empty() && running() == 0) break;
+        if (running() == 0 && (pending.empty() || stop)) {
+            cv_work.wait(lk);
+        } else {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+extern "C" {
+
+int psdproj_serve_create(const psdproj_serve_config *cfg, psdproj_server **out) {
+    if (!out) return PSDPROJ_ERR_INVALID_ARG;
+    psdproj_server *s = new psdproj_server();
+    if (cfg) s->cfg = *cfg;
+    if (!s->cfg.hbm_budget_bytes) s->cfg.hbm_budget_bytes = (size_t)200 << 30;
+    if (s->cfg.slots <= 0) s->cfg.slots = 4;
+    if (s->cfg.slots > 64) { delete s; return PSDPROJ_ERR_INVALID_ARG; }
+    if (s->cfg.max_bypass <= 0) s->cfg.max_bypass = 8;
+    if (s->cfg.fake_tflops <= 0.0) s->cfg.fake_tflops = 500.0;
+    s->slots.resize(s->cfg.slots);
+    if (!s->cfg.fake_executor) {
+        if (hipGetDevice(&s->device) != hipSuccess) { delete s; return PSDPROJ_ERR_HIP; }
+        for (Slot &sl : s->slots) {
+            if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+                for (Slot &x : s->slots) {
+                    if (x.done) (void)hipEventDestroy(x.done);
+                    if (x.stream) (void)hipStreamDestroy(x.stream);
+                }
+                delete s;
+                return PSDPROJ_ERR_HIP;
+            }
+        }
+    }
+    s->th = std::thread([s] { s->loop(); });
+    *out = s;
+    return PSDPROJ_OK;
+}
+
+int psdproj_serve_submit(psdproj_server *s, const psdproj_request *r, uint64_t *ticket) {
+    if (!s || !r || !ticket) return PSDPROJ_ERR_INVALID_ARG;
+    if (r->n < 0 || r->ld < (r->n > 1 ? r->n : 1) || (r->n > 0 && !s->cfg.fake_executor && (!r->X || !r->out)))
+        return PSDPROJ_ERR_INVALID_ARG;
+    const int mode = choose_mode(*r);
+    const size_t ws = psd::workspace_bytes_for(r->n > 0 ? r->n : 1, mode);
+    if (ws == 0) return PSDPROJ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return PSDPROJ_ERR_CANCELLED;
+    ++s->n_sub;
+    if (ws > s->cfg.hbm_budget_bytes) {
+        ++s->n_rej;
+        return PSDPROJ_ERR_REJECTED;
+    }
+    const uint64_t tk = s->next_ticket++;
+    Req &q = s->reqs[tk];
+    q.r = *r;
+    q.mode = mode;
+    q.ws = ws;
+    q.submit_ns = now_ns();
+    if (!s->first_submit) s->first_submit = q.submit_ns;
+    s->pending.push_back(tk);
+    *ticket = tk;
+    s->cv_work.notify_one();
+    return PSDPROJ_OK;
+}
+
+static void fill_result(const Req &q, psdproj_result *res) {
+    if (!res) return;
+    res->status = q.status;
+    res->mode = q.mode;
+    res->tag = q.r.tag;
+    res->submit_ns = q.submit_ns;
+    res->start_ns = q.start_ns;
+    res->end_ns = q.end_ns;
+    res->slot = q.slot;
+}
+
+int psdproj_serve_wait(psdproj_server *s, uint64_t ticket, int64_t timeout_ns, psdproj_result *res) {
+    if (!s) return PSDPROJ_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return PSDPROJ_ERR_NOT_FOUND;
+    auto done = [&] { auto j = s->reqs.find(ticket); return j == s->reqs.end() || j->second.finished; };
+    if (timeout_ns < 0) {
+        s->cv_done.wait(lk, done);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
+        return PSDPROJ_ERR_TIMEOUT;
+    }
+    it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return PSDPROJ_ERR_NOT_FOUND;
+    fill_result(it->second, res);
+    s->reqs.erase(it);
+    return PSDPROJ_OK;
+}
+
+int psdproj_serve_poll(psdproj_server *s, uint64_t ticket, psdproj_result *res) {
+    if (!s) return PSDPROJ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return PSDPROJ_ERR_NOT_FOUND;
+    if (!it->second.finished) return PSDPROJ_ERR_PENDING;
+    fill_result(it->second, res);
+    s->reqs.erase(it);
+    return PSDPROJ_OK;
+}
+
+int psdproj_serve_cancel(psdproj_server *s, uint64_t ticket) {
+    if (!s) return PSDPROJ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return PSDPROJ_ERR_NOT_FOUND;
+    if (it->second.finished) return PSDPROJ_OK;
+    auto pit = std::find(s->pending.begin(), s->pending.end(), ticket);
+    if (pit == s->pending.end()) return PSDPROJ_ERR_PENDING;  // already running
+    s->pending.erase(pit);
+    it->second.status = PSDPROJ_ERR_CANCELLED;
+    it->second.finished = true;
+    it->second.end_ns = now_ns();
+    ++s->n_cancel;
+    s->cv_done.notify_all();
+    return PSDPROJ_OK;
+}
+
+int psdproj_serve_stats(psdproj_server *s, psdproj_serve_statistics *st) {
+    if (!s || !st) return PSDPROJ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *st = psdproj_serve_statistics{};
+    st->submitted = s->n_sub;
+    st->completed = s->n_done;
+    st->rejected = s->n_rej;
+    st->cancelled = s->n_cancel;
+    st->pending = s->pending.size();
+    st->running = (uint64_t)s->running();
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            const double pos = p * (double)(v.size() - 1);
+            const size_t i = (size_t)pos;
+            const double f = pos - (double)i;
+            return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+        };
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+        double sum = 0.0;
+        for (double x : v) sum += x;
+        st->mean_ms = sum / (double)v.size();
+        st->max_ms = v.back();
+        const double span = (double)(s->last_end - s->first_submit) * 1e-9;
+        st->throughput_per_s = span > 0.0 ? (double)s->n_done / span : 0.0;
+    }
+    st->bytes_held = s->held_total();
+    st->peak_bytes_held = s->peak_held;
+    return PSDPROJ_OK;
+}
+
+int psdproj_serve_destroy(psdproj_server *s) {
+    if (!s) return PSDPROJ_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (uint64_t tk : s->pending) {
+            Req &q = s->reqs[tk];
+            q.status = PSDPROJ_ERR_CANCELLED;
+            q.finished = true;
+            ++s->n_cancel;
+        }
+        s->pending.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    s->th.join();  // the loop exits once running work has completed
+    if (!s->cfg.fake_executor) {
+        for (Slot &sl : s->slots) {
+            psd::pool_release(sl.stream);
+            (void)hipEventDestroy(sl.done);
+            (void)hipStreamDestroy(sl.stream);
+        }
+    }
+    delete s;
+    return PSDPROJ_OK;
+}
+
+}  // extern "C"

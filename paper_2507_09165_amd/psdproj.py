@@ -214,3 +214,110 @@ def sym_gemm(dtype, L, R, D, Llo=None, Rlo=None, C0=None, C0lo=None, Dlo=None,
                                   _ptr(C0), _ptr(C0lo), float(alpha), float(beta), float(gamma),
                                   _ptr(D), _ptr(Dlo), _stream(stream)), "psdproj_sym_gemm")
     return D
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int),
+                ("max_bypass", ctypes.c_int), ("fake_executor", ctypes.c_int),
+                ("fake_tflops", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("X", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("target", ctypes.c_double), ("mode", ctypes.c_int),
+                ("tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("mode", ctypes.c_int), ("tag", ctypes.c_uint64),
+                ("submit_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64), ("end_ns", ctypes.c_int64),
+                ("slot", ctypes.c_int)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
+                ("pending", ctypes.c_uint64), ("running", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("throughput_per_s", ctypes.c_double),
+                ("bytes_held", ctypes.c_size_t), ("peak_bytes_held", ctypes.c_size_t)]
+
+
+def _serve_sigs(L):
+    vp = ctypes.c_void_p
+    L.psdproj_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    L.psdproj_serve_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.psdproj_serve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(Result)]
+    L.psdproj_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.psdproj_serve_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.psdproj_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.psdproj_serve_destroy.argtypes = [vp]
+    for nm in ("create", "submit", "wait", "poll", "cancel", "stats", "destroy"):
+        getattr(L, "psdproj_serve_" + nm).restype = ctypes.c_int
+
+
+def _res_dict(r: Result) -> dict:
+    return {k: getattr(r, k) for k, _ in Result._fields_}
+
+
+class Server:
+    """Continuous-batching projection server (psdproj_serve_*)."""
+
+    def __init__(self, hbm_budget_bytes=0, slots=0, max_bypass=0, fake_executor=False, fake_tflops=0.0):
+        L = lib()
+        _serve_sigs(L)
+        self._L = L
+        cfg = ServeConfig(int(hbm_budget_bytes), int(slots), int(max_bypass), int(bool(fake_executor)),
+                          float(fake_tflops))
+        h = ctypes.c_void_p()
+        _check(L.psdproj_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "psdproj_serve_create")
+        self._h = h
+
+    def submit(self, n, X=None, out=None, target=1e-3, mode=-1, tag=0, ld=None):
+        """Returns a ticket, or raises PsdprojError (e.g. status 5 = rejected)."""
+        if X is not None:
+            n, ld = _check_matrix(X)
+        req = Request(int(n), int(ld if ld is not None else max(1, n)),
+                      None if X is None else X.data_ptr(), None if out is None else out.data_ptr(),
+                      float(target), _mode(mode) if isinstance(mode, str) else int(mode), int(tag))
+        tk = ctypes.c_uint64()
+        _check(self._L.psdproj_serve_submit(self._h, ctypes.byref(req), ctypes.byref(tk)), "psdproj_serve_submit")
+        return tk.value
+
+    def wait(self, ticket, timeout_s=None):
+        r = Result()
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        st = self._L.psdproj_serve_wait(self._h, ticket, t, ctypes.byref(r))
+        if st != 0:
+            raise PsdprojError(st, "psdproj_serve_wait")
+        return _res_dict(r)
+
+    def poll(self, ticket):
+        r = Result()
+        st = self._L.psdproj_serve_poll(self._h, ticket, ctypes.byref(r))
+        if st == 9:
+            return None
+        _check(st, "psdproj_serve_poll")
+        return _res_dict(r)
+
+    def cancel(self, ticket) -> int:
+        return int(self._L.psdproj_serve_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        _check(self._L.psdproj_serve_stats(self._h, ctypes.byref(s)), "psdproj_serve_stats")
+        return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(self._L.psdproj_serve_destroy(self._h), "psdproj_serve_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
