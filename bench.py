@@ -128,6 +128,102 @@ def cpu_baseline(mode, n_sample):
                       f"scaled by (10000/{n_sample})^3"}
 
 
+def batched_leg(steps=3, warmup=1, count=256, mode="bf16"):
+    """256 independent GOE blocks, n log-uniform in [32, 1024] (seed 7): one
+    psdproj_project_batched call per step; projections per second."""
+    import torch
+    from paper_2507_09165_amd import inputs
+    from paper_2507_09165_amd import psdproj as P
+    sizes = inputs.batch_sizes(count, 7)
+    Xs = [torch.from_numpy(B).cuda() for B in inputs.batch_blocks(sizes, 7)]
+    outs = [torch.empty_like(X) for X in Xs]
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.project_batched(Xs, outs, mode=mode, stream=st)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    for _ in range(steps):
+        P.project_batched(Xs, outs, mode=mode, stream=st)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    flops = sum(P.gemm_count(mode) * float(n) * n * (n + 1) for n in sizes)
+    return {"workload": f"{count} GOE blocks, n log-uniform in [32, 1024] (seed 7), {mode}",
+            "ms_per_batch": ms, "host_ms_per_batch": wall, "proj_per_s": count / (ms * 1e-3),
+            "algorithmic_tflops": flops / (ms * 1e-3) / 1e12, "n_min": int(sizes.min()),
+            "n_max": int(sizes.max()), "steps": steps}
+
+
+def serving_leg(num=600, rho=(0.8,), clients=8, slots=4, seed=11):
+    """Poisson arrivals at rho * mu (mu: measured saturated throughput) of
+    requests from `clients` ADMM-like iterate streams (n log-uniform in
+    [64, 8192]; Y_k = Y_{k-1} + sqrt(1e-3) GOE_k, 8 iterates per client kept
+    in HBM), target 1e-3 (FP16_SPLIT) or 1e-5 (FP32) drawn 70/30; admitted
+    under a 200 GB budget. Reports p50/p99 latency and projections/s."""
+    import threading
+    import torch
+    from paper_2507_09165_amd import psdproj as P
+    rng = np.random.default_rng(seed)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    cn = np.clip(np.rint(np.exp(rng.uniform(np.log(64), np.log(8192), size=clients))), 64, 8192).astype(int)
+
+    def goe_dev(n):
+        G = torch.randn(n, n, device="cuda", generator=g)
+        return (G + G.t()) * (1.0 / np.sqrt(2.0 * n))
+
+    iters = []
+    for n in cn:
+        Y = goe_dev(int(n))
+        seq = [Y]
+        for _ in range(7):
+            Y = Y + np.sqrt(1e-3) * goe_dev(int(n))
+            seq.append(Y)
+        iters.append(seq)
+    outs = [[torch.empty_like(Y) for Y in seq] for seq in iters]
+    torch.cuda.synchronize()
+
+    def trace(k):
+        c = rng.integers(clients, size=k)
+        t = np.where(rng.uniform(size=k) < 0.7, 1e-3, 1e-5)
+        return c, t
+
+    def run(k, rate):
+        c, t = trace(k)
+        gaps = rng.exponential(1.0 / rate, size=k) if rate else np.zeros(k)
+        with P.Server(slots=slots) as srv:
+            tks = []
+            t0 = time.perf_counter()
+            due = t0
+            for i in range(k):
+                due += gaps[i]
+                dt = due - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                j = i % 8
+                tks.append(srv.submit(X=iters[c[i]][j], out=outs[c[i]][j], target=float(t[i]), tag=i))
+            for tk in tks:
+                r = srv.wait(tk, timeout_s=600)
+                assert r["status"] == 0, r
+            stt = srv.stats()
+        return stt
+
+    run(max(8, clients), 0)  # warm the slots' workspaces
+    sat = run(min(num, 300), 0)
+    mu = sat["throughput_per_s"]
+    res = {"workload": f"{clients} ADMM-like client streams, n in {sorted(int(x) for x in cn)}, "
+                       f"Poisson arrivals, 70% target 1e-3 / 30% 1e-5, {slots} slots, 200 GB budget",
+           "saturated_proj_per_s": mu, "runs": []}
+    for r_ in rho:
+        stt = run(num, r_ * mu)
+        res["runs"].append({"rho": r_, "offered_per_s": r_ * mu, "proj_per_s": stt["throughput_per_s"],
+                            "p50_ms": stt["p50_ms"], "p99_ms": stt["p99_ms"], "mean_ms": stt["mean_ms"],
+                            "requests": int(stt["completed"]), "peak_workspace_gb": stt["peak_bytes_held"] / 1e9})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +237,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rocsolver", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X; this build has no multi-GPU path (--gpus must be 1).",
@@ -216,6 +315,14 @@ def main():
             del P32
         res["rocsolver"] = roc
     res["paper_context"] = {"b200_fp16_ms": 54.8, "b200_fp32_emulated_ms": 416.0, "n": 10000}
+    del X, out
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched leg")
+        res["batched"] = batched_leg()
+    if not args.no_serve:
+        log("serving leg")
+        res["serving"] = serving_leg(num=args.serve_requests)
     if not args.no_cpu:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(args.mode, args.cpu_sample)

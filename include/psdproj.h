@@ -60,8 +60,11 @@ typedef enum {
     PSDPROJ_MODE_FP32 = 0,       /* Table 1 refined (T = 10), FP32 MFMA, 31 products  */
     PSDPROJ_MODE_FP16 = 1,       /* Table 2 refined (T = 7), FP16 MFMA, 22 products   */
     PSDPROJ_MODE_BF16 = 2,       /* Table 2 refined (T = 7), BF16 MFMA, 22 products   */
-    PSDPROJ_MODE_FP16_SPLIT = 3  /* Table 2 refined, FP16 with hi+lo split operands in
+    PSDPROJ_MODE_FP16_SPLIT = 3, /* Table 2 refined, FP16 with hi+lo split operands in
                                     the stages of split_mask and the final product   */
+    PSDPROJ_MODE_FP32_EMU = 4    /* Table 1 refined (T = 10), every product on FP16
+                                    hi+lo pairs (FP32-level operands at the FP16
+                                    MFMA rate), 93 product-equivalents              */
 } psdproj_mode;
 
 typedef struct {

@@ -123,5 +123,5 @@ MODE_TABLE = {
     "fp16": "f_tilde_half",
     "bf16": "f_tilde_half",
     "fp16_split": "f_tilde_half",
-    "fp8_fp16_split": "f_tilde_half",
+    "fp32_emu": "f_tilde_single",
 }

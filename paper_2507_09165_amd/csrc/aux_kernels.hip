@@ -1,18 +1,20 @@
-// Bandwidth-bound kernels of the projection: triangle mirror / rescale-and-cast,
-// and the FP64 Lanczos run that yields the spectral bound.
+// Bandwidth-bound kernels of the projection: the FP64 Lanczos run that yields
+// the spectral bound, and the rescale-and-cast of X into the work precision.
 //
-//  * mirror_cast: reads the upper triangle of X (column-major, ld) in 64 x 64
-//    tiles, writes the full symmetric matrix scaled by s (1 for the FP32 copy
-//    the Lanczos matvecs read, 1/lam for X0 = X / lam of Algorithm 2), rounded
-//    to the work precision, optionally as a hi + lo pair, zero-padded to n_p.
-//  * Lanczos on X^2 (Section 3.4 and Algorithm 2, first two steps): 20 steps
-//    of w = X (X v) in FP64 with full reorthogonalisation (two classical
+//  * Lanczos on X^2 (Section 3.4; Algorithm 2, first two steps): 20 steps of
+//    w = X (X v) in FP64 with full reorthogonalisation (two classical
 //    Gram-Schmidt passes), the largest Ritz pair (sigma, q) of the tridiagonal,
-//    and the bound lam = sqrt(sigma + ||X (X q) - sigma q||) of Theorem 2.
-//    The first matvec also produces the column norms: ||X||_F and the lower
-//    bound max_j ||X e_j|| that guards the heuristic bound.
-// All reductions are fixed-order (no floating-point atomics), so results are
-// bitwise reproducible run to run.
+//    and the bound lam = sqrt(sigma + ||X (X q) - sigma q||) of Theorem 2. The
+//    matvecs read only the upper triangle of the caller's FP32 X; the first
+//    one also yields the column norms (||X||_F and the lower bound
+//    max_j ||X e_j|| that guards the heuristic bound).
+//  * mirror_cast: X0 = X / lam from the upper triangle in 64 x 64 tiles, full
+//    symmetric, rounded to the work precision (optionally a hi + lo pair),
+//    zero-padded to n_p (Algorithm 2, rescale step).
+// Every kernel takes the batch's descriptor table and a work list mapping
+// each workgroup to (matrix, local block); a single projection is a batch of
+// one. All reductions are fixed-order (no floating-point atomics), so results
+// are bitwise reproducible and independent of what else is in the batch.
 #include <math.h>
 
 #include "aux_kernels.hpp"
@@ -20,190 +22,16 @@
 
 namespace psd {
 
-// ---------------------------------------------------------------------------
-// mirror / rescale / cast
-// ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ T cvt(float v) { return (T)v; }
+constexpr int kRows = 256;  // rows per block in the vector kernels
+constexpr int kTB = 128;    // tile edge of the symmetric matvec
 
-template <typename T, bool SPLIT>
-__global__ __launch_bounds__(256) void mirror_cast_kernel(const float *__restrict__ X, int64_t ldx, int64_t n,
-                                                          const Scalars *scal, int use_inv_lam, T *__restrict__ Ohi,
-                                                          T *__restrict__ Olo, int64_t ldo, float lo_scale) {
-    __shared__ float tile[64][65];
-    // upper-triangle tile pairs over the padded size, column by column
-    const int t = blockIdx.x;
-    int bj = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
-    while (bj * (bj + 1) / 2 > t) --bj;
-    const int bi = t - bj * (bj + 1) / 2;
-    const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
-    const float s = use_inv_lam ? (float)scal->inv_lam : 1.0f;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-    // load: element (i0 + tx, j0 + c) = X[(j0 + c) * ldx + i0 + tx], upper part only
-    for (int c = ty; c < 64; c += 4) {
-        const int64_t i = i0 + tx, j = j0 + c;
-        float v = 0.0f;
-        if (i < n && j < n && i <= j) v = X[j * ldx + i];
-        tile[tx][c] = v;
-    }
-    __syncthreads();
-    if (bi == bj) {  // complete the diagonal tile from its upper half
-        for (int c = ty; c < 64; c += 4)
-            if (tx > c) tile[tx][c] = tile[c][tx];
-        __syncthreads();
-    }
-    // direct write: O(i0 + tx, j0 + c) at column j0 + c
-    for (int c = ty; c < 64; c += 4) {
-        const float v = tile[tx][c] * s;
-        const T hi = cvt<T>(v);
-        Ohi[(j0 + c) * ldo + i0 + tx] = hi;
-        if constexpr (SPLIT) Olo[(j0 + c) * ldo + i0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
-    }
-    if (bi == bj) return;
-    // mirrored write: O(j0 + tx, i0 + c) = tile[c][tx]
-    for (int c = ty; c < 64; c += 4) {
-        const float v = tile[c][tx] * s;
-        const T hi = cvt<T>(v);
-        Ohi[(i0 + c) * ldo + j0 + tx] = hi;
-        if constexpr (SPLIT) Olo[(i0 + c) * ldo + j0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
-    }
-}
-
-template <typename T, bool SPLIT>
-static hipError_t mirror_cast_t(const float *X, int64_t ldx, int64_t n, int64_t n_out, const Scalars *scal,
-                                int use_inv_lam, void *Ohi, void *Olo, int64_t ldo, float lo_scale, hipStream_t s) {
-    const int64_t nt = (n_out + 63) / 64;
-    const int64_t ntiles = nt * (nt + 1) / 2;
-    if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((mirror_cast_kernel<T, SPLIT>), dim3((unsigned)ntiles), dim3(256), 0, s, X, ldx, n, scal,
-                       use_inv_lam, (T *)Ohi, (T *)Olo, ldo, lo_scale);
-    return hipGetLastError();
-}
-
-hipError_t mirror_cast(const float *X, int64_t ldx, int64_t n, int64_t n_out, const Scalars *scal, int use_inv_lam,
-                       int dtype, void *Ohi, void *Olo, int64_t ldo, hipStream_t s) {
-    if (n_out % 64) return hipErrorInvalidValue;
-    switch (dtype) {
-        case 0: return mirror_cast_t<float, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
-        case 1:
-            return Olo ? mirror_cast_t<f16, true>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, Olo, ldo, 2048.0f, s)
-                       : mirror_cast_t<f16, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
-        case 2:
-            return Olo ? mirror_cast_t<bf16, true>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, Olo, ldo, 1.0f, s)
-                       : mirror_cast_t<bf16, false>(X, ldx, n, n_out, scal, use_inv_lam, Ohi, nullptr, ldo, 1.0f, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-// ---------------------------------------------------------------------------
-// Lanczos
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
-// z_i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15); v_i = 2 (z_i >> 11) 2^-53 - 1.
-__device__ __forceinline__ double start_entry(uint64_t i, uint64_t seed) {
-    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z = z ^ (z >> 31);
-    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric matvec from the upper triangle. The triangle is cut into
-// kTB x kTB tiles (I <= J, enumerated column by column: t = J (J + 1) / 2 + I).
-// Tile (I, J) reads its upper part once and produces
-//   d[t][c] = sum_{i in I} X(i, j0 + c) v_i           (column dots)
-//   a[t][r] = sum_{j in J} X(i0 + r, j) v_j           (row sums, i < j only)
-// and y_k = sum_{I <= K} d[tile(I, K)][k] + sum_{J >= K} a[tile(K, J)][k],
-// summed in that fixed order by symv_reduce_kernel. With NORMS the same is
-// done for X(i, j)^2 and v = 1, which yields the full column norms.
-// ---------------------------------------------------------------------------
-constexpr int kTB = 128;
-
-__device__ __forceinline__ void tile_of(int t, int &I, int &J) {
-    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    while ((j + 1) * (j + 2) / 2 <= t) ++j;
-    while (j * (j + 1) / 2 > t) --j;
-    J = j;
-    I = t - j * (j + 1) / 2;
-}
-
-template <bool NORMS>
-__global__ __launch_bounds__(256) void symv_tile_kernel(const float *__restrict__ X, int64_t ld, int64_t n,
-                                                        const double *__restrict__ v, const double *vscale,
-                                                        double *__restrict__ d, double *__restrict__ a,
-                                                        double *__restrict__ d2, double *__restrict__ a2,
-                                                        const Scalars *scal, int stop_on_flag) {
-    if (stop_on_flag && scal->stop) return;
-    const int t = blockIdx.x;
-    int I, J;
-    tile_of(t, I, J);
-    const int64_t i0 = (int64_t)I * kTB, j0 = (int64_t)J * kTB;
-    const bool diag = (I == J);
-    __shared__ double vI[kTB], vJ[kTB];
-    __shared__ double red[4][kTB], red2[4][kTB];
-    const double sc = vscale ? *vscale : 1.0;
-    if (threadIdx.x < kTB) {
-        const int64_t i = i0 + threadIdx.x;
-        vI[threadIdx.x] = i < n ? v[i] * sc : 0.0;
-    } else {
-        const int64_t j = j0 + threadIdx.x - kTB;
-        vJ[threadIdx.x - kTB] = j < n ? v[j] * sc : 0.0;
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = 2 * lane;  // this lane's two rows of the tile
-    const int64_t ia = i0 + r0, ib = ia + 1;
-    double ax0 = 0.0, ax1 = 0.0, sq0 = 0.0, sq1 = 0.0;
-    const double via = vI[r0], vib = vI[r0 + 1];
-    // wave w handles tile columns c = 32 w .. 32 w + 31
-#pragma unroll 8
-    for (int cc = 0; cc < 32; ++cc) {
-        const int c = 32 * wave + cc;
-        const int64_t j = j0 + c;
-        float x0 = 0.0f, x1 = 0.0f;
-        if (j < n) {
-            const float *col = X + j * ld;
-            if (ia < n && (!diag || ia <= j)) x0 = col[ia];
-            if (ib < n && (!diag || ib <= j)) x1 = col[ib];
-        }
-        const double dot = wave_sum((double)x0 * via + (double)x1 * vib);
-        const double vj = vJ[c];
-        // row sums: strictly upper entries only (the diagonal is in the dot)
-        const bool u0 = !diag || ia < j, u1 = !diag || ib < j;
-        ax0 += u0 ? (double)x0 * vj : 0.0;
-        ax1 += u1 ? (double)x1 * vj : 0.0;
-        if (lane == 0) d[(int64_t)t * kTB + c] = dot;
-        if constexpr (NORMS) {
-            const double q = wave_sum((double)x0 * x0 + (double)x1 * x1);
-            sq0 += u0 ? (double)x0 * x0 : 0.0;
-            sq1 += u1 ? (double)x1 * x1 : 0.0;
-            if (lane == 0) d2[(int64_t)t * kTB + c] = q;
-        }
-    }
-    red[wave][r0] = ax0;
-    red[wave][r0 + 1] = ax1;
-    if constexpr (NORMS) {
-        red2[wave][r0] = sq0;
-        red2[wave][r0 + 1] = sq1;
-    }
-    __syncthreads();
-    if (threadIdx.x < kTB) {
-        const int r = threadIdx.x;
-        a[(int64_t)t * kTB + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
-        if constexpr (NORMS) a2[(int64_t)t * kTB + r] = red2[0][r] + red2[1][r] + red2[2][r] + red2[3][r];
-    }
-}
-
-constexpr int kRows = 256;  // rows per block in the vector kernels
-
-// Block reduction of NV doubles per thread into out[0..NV) (thread 0 holds it).
+// Block reduction of NV doubles per thread (thread 0 holds the result).
 template <int NV>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], double *sh /* [4][NV] */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -225,125 +53,293 @@ __device__ __forceinline__ double sum_partials(const double *part, int nb, int s
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// rescale / cast
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T cvt(float v) { return (T)v; }
+
+// Upper-triangle tile index -> (I, J), column by column: t = J (J + 1) / 2 + I.
+__device__ __forceinline__ void tile_of(int t, int &I, int &J) {
+    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    while (j * (j + 1) / 2 > t) --j;
+    J = j;
+    I = t - j * (j + 1) / 2;
+}
+
+// Slot 0 of matrix m <- X / lam (64 x 64 tile pair (bi <= bj) of the padded
+// n_p x n_p matrix, transposed through LDS for the mirrored half).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
+                                                   IoArg io0, float lo_scale) {
+    __shared__ float tile[64][65];
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &d = D[wi.x];
+    const IoArg io = io_of(io_tab, io0, wi.x);
+    int bi, bj;
+    tile_of((int)wi.y, bi, bj);
+    const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64, n = d.n, ldo = d.ldw;
+    const float s = (float)d.scal->inv_lam;
+    T *Ohi = (T *)d.hi[0];
+    T *Olo = (T *)d.lo[0];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int c = ty; c < 64; c += 4) {
+        const int64_t i = i0 + tx, j = j0 + c;
+        float v = 0.0f;
+        if (i < n && j < n && i <= j) v = io.X[j * io.ld + i];
+        tile[tx][c] = v;
+    }
+    __syncthreads();
+    if (bi == bj) {  // complete the diagonal tile from its upper half
+        for (int c = ty; c < 64; c += 4)
+            if (tx > c) tile[tx][c] = tile[c][tx];
+        __syncthreads();
+    }
+    for (int c = ty; c < 64; c += 4) {
+        const float v = tile[tx][c] * s;
+        const T hi = cvt<T>(v);
+        Ohi[(j0 + c) * ldo + i0 + tx] = hi;
+        if constexpr (SPLIT) Olo[(j0 + c) * ldo + i0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
+    }
+    if (bi == bj) return;
+    for (int c = ty; c < 64; c += 4) {
+        const float v = tile[c][tx] * s;
+        const T hi = cvt<T>(v);
+        Ohi[(i0 + c) * ldo + j0 + tx] = hi;
+        if constexpr (SPLIT) Olo[(i0 + c) * ldo + j0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
+// z_i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15); v_i = 2 (z_i >> 11) 2^-53 - 1.
+__device__ __forceinline__ double start_entry(uint64_t i, uint64_t seed) {
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+// Input vector of a symmetric matvec.
+enum SymvSrc { SRC_V = 0, SRC_U = 1, SRC_W = 2, SRC_QHAT = 3 };
+// Output vector of the reduction.
+enum SymvDst { DST_U = 0, DST_W = 1, DST_W2 = 2 };
+
+// Symmetric matvec from the upper triangle. The triangle is cut into
+// kTB x kTB tiles (I <= J, t = J (J + 1) / 2 + I). Tile (I, J) reads its upper
+// part once and produces
+//   d[t][c] = sum_{i in I} X(i, j0 + c) v_i           (column dots)
+//   a[t][r] = sum_{j in J} X(i0 + r, j) v_j           (row sums, i < j only)
+// and y_k = sum_{I <= K} d[tile(I, K)][k] + sum_{J >= K} a[tile(K, J)][k],
+// summed in that fixed order by symv_reduce_kernel. With NORMS the same is
+// done for X(i, j)^2 and v = 1, which yields the full column norms.
+template <bool NORMS>
+__global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
+                                                        IoArg io0, int src, int jstep, int stop_on_flag) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    if (stop_on_flag && dm.scal->stop) return;
+    const IoArg io = io_of(io_tab, io0, wi.x);
+    const int64_t n = dm.n;
+    const int t = (int)wi.y;
+    int I, J;
+    tile_of(t, I, J);
+    const int64_t i0 = (int64_t)I * kTB, j0 = (int64_t)J * kTB;
+    const bool diag = (I == J);
+    const double *v = src == SRC_V ? dm.V + (int64_t)jstep * n : (src == SRC_W ? dm.w : dm.u);
+    const double sc = src == SRC_QHAT ? dm.scal->qnorm_inv : 1.0;
+    __shared__ double vI[kTB], vJ[kTB];
+    __shared__ double red[4][kTB], red2[4][kTB];
+    if (threadIdx.x < kTB) {
+        const int64_t i = i0 + threadIdx.x;
+        vI[threadIdx.x] = i < n ? v[i] * sc : 0.0;
+    } else {
+        const int64_t j = j0 + threadIdx.x - kTB;
+        vJ[threadIdx.x - kTB] = j < n ? v[j] * sc : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = 2 * lane;  // this lane's two rows of the tile
+    const int64_t ia = i0 + r0, ib = ia + 1;
+    double ax0 = 0.0, ax1 = 0.0, sq0 = 0.0, sq1 = 0.0;
+    const double via = vI[r0], vib = vI[r0 + 1];
+    double *dd = dm.sd + (int64_t)t * kTB;
+#pragma unroll 8
+    for (int cc = 0; cc < 32; ++cc) {  // wave w handles tile columns 32 w .. 32 w + 31
+        const int c = 32 * wave + cc;
+        const int64_t j = j0 + c;
+        float x0 = 0.0f, x1 = 0.0f;
+        if (j < n) {
+            const float *col = io.X + j * io.ld;
+            if (ia < n && (!diag || ia <= j)) x0 = col[ia];
+            if (ib < n && (!diag || ib <= j)) x1 = col[ib];
+        }
+        const double dot = wave_sum((double)x0 * via + (double)x1 * vib);
+        const double vj = vJ[c];
+        // row sums: strictly upper entries only (the diagonal is in the dot)
+        const bool u0 = !diag || ia < j, u1 = !diag || ib < j;
+        ax0 += u0 ? (double)x0 * vj : 0.0;
+        ax1 += u1 ? (double)x1 * vj : 0.0;
+        if (lane == 0) dd[c] = dot;
+        if constexpr (NORMS) {
+            const double q = wave_sum((double)x0 * x0 + (double)x1 * x1);
+            sq0 += u0 ? (double)x0 * x0 : 0.0;
+            sq1 += u1 ? (double)x1 * x1 : 0.0;
+            if (lane == 0) dm.sd2[(int64_t)t * kTB + c] = q;
+        }
+    }
+    red[wave][r0] = ax0;
+    red[wave][r0 + 1] = ax1;
+    if constexpr (NORMS) {
+        red2[wave][r0] = sq0;
+        red2[wave][r0 + 1] = sq1;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTB) {
+        const int r = threadIdx.x;
+        dm.sa[(int64_t)t * kTB + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
+        if constexpr (NORMS) dm.sa2[(int64_t)t * kTB + r] = red2[0][r] + red2[1][r] + red2[2][r] + red2[3][r];
+    }
+}
+
 // y_k from the symv tile partials (fixed order: column dots of tiles I <= K,
 // then row sums of tiles J >= K). NORMS: also colsq_k. ORTH0: also the first
-// Gram-Schmidt partials part[block][c] = sum over this block's rows of
-// V[i, c] y_i, c <= jstep (the block covers kRows rows).
+// Gram-Schmidt partials pa[block][c] = sum over this block's rows of
+// V[i, c] y_i, c <= jstep.
 template <bool NORMS, bool ORTH0>
-__global__ __launch_bounds__(256) void symv_reduce_kernel(int64_t n, const double *__restrict__ d,
-                                                          const double *__restrict__ a, const double *__restrict__ d2,
-                                                          const double *__restrict__ a2, double *__restrict__ y,
-                                                          double *__restrict__ colsq, const double *__restrict__ V,
-                                                          int jstep, double *__restrict__ part, const Scalars *scal,
+__global__ __launch_bounds__(256) void symv_reduce_kernel(const MatDesc *D, const WorkItem *W, int dst, int jstep,
                                                           int stop_on_flag) {
-    if (stop_on_flag && scal->stop) return;
-    const int64_t k = (int64_t)blockIdx.x * kRows + threadIdx.x;
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    if (stop_on_flag && dm.scal->stop) return;
+    const int64_t n = dm.n;
+    const int b = (int)wi.y;
+    const int64_t k = (int64_t)b * kRows + threadIdx.x;
     const int T = (int)((n + kTB - 1) / kTB);
+    double *y = dst == DST_U ? dm.u : (dst == DST_W ? dm.w : dm.w2);
     double yk = 0.0, ck = 0.0;
     if (k < n) {
         const int K = (int)(k / kTB), kk = (int)(k % kTB);
         const int64_t base = (int64_t)K * (K + 1) / 2;
         for (int I = 0; I <= K; ++I) {
-            yk += d[(base + I) * kTB + kk];
-            if constexpr (NORMS) ck += d2[(base + I) * kTB + kk];
+            yk += dm.sd[(base + I) * kTB + kk];
+            if constexpr (NORMS) ck += dm.sd2[(base + I) * kTB + kk];
         }
         for (int J = K; J < T; ++J) {
             const int64_t t = (int64_t)J * (J + 1) / 2 + K;
-            yk += a[t * kTB + kk];
-            if constexpr (NORMS) ck += a2[t * kTB + kk];
+            yk += dm.sa[t * kTB + kk];
+            if constexpr (NORMS) ck += dm.sa2[t * kTB + kk];
         }
         y[k] = yk;
-        if constexpr (NORMS) colsq[k] = ck;
+        if constexpr (NORMS) dm.colsq[k] = ck;
     }
     if constexpr (ORTH0) {
         __shared__ double red[4 * kMaxLanczos];
         double h[kMaxLanczos];
 #pragma unroll
-        for (int c = 0; c < kMaxLanczos; ++c) h[c] = (c <= jstep && k < n) ? V[(int64_t)c * n + k] * yk : 0.0;
+        for (int c = 0; c < kMaxLanczos; ++c) h[c] = (c <= jstep && k < n) ? dm.V[(int64_t)c * n + k] * yk : 0.0;
         block_reduce<kMaxLanczos>(h, red);
         if (threadIdx.x == 0)
-            for (int c = 0; c <= jstep; ++c) part[(int64_t)blockIdx.x * kMaxLanczos + c] = h[c];
+            for (int c = 0; c <= jstep; ++c) dm.pa[(int64_t)b * kMaxLanczos + c] = h[c];
     }
 }
 
-// Start vector: V[:, 0] = v / ||v||. Pass 0 writes v and the partial norms,
-// pass 1 normalises.
-__global__ __launch_bounds__(256) void lz_start_kernel(double *V, int64_t n, double *part, int pass, uint64_t seed) {
-    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+__global__ void scal_init_kernel(const MatDesc *D) {
+    if (threadIdx.x == 0) {
+        Scalars z = {};
+        *D[blockIdx.x].scal = z;
+    }
+}
+
+// Start vector: V[:, 0] = v / ||v||. Pass 0 writes v and the partial norms
+// (pa), pass 1 normalises.
+__global__ __launch_bounds__(256) void lz_start_kernel(const MatDesc *D, const WorkItem *W, int pass, uint64_t seed) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    const int b = (int)wi.y;
+    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
     __shared__ double sh[4];
     if (pass == 0) {
         double x[1] = {0.0};
         if (i < n) {
             const double e = start_entry((uint64_t)i, seed);
-            V[i] = e;
+            dm.V[i] = e;
             x[0] = e * e;
         }
         block_reduce<1>(x, sh);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+        if (threadIdx.x == 0) dm.pa[(int64_t)b * kMaxLanczos] = x[0];
     } else {
-        const double nrm = sqrt(sum_partials(part, gridDim.x, kMaxLanczos, 0));
-        if (i < n) V[i] = V[i] / nrm;
+        const double nrm = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
+        if (i < n) dm.V[i] = dm.V[i] / nrm;
     }
 }
 
-// Orthogonalisation pass of step j over rows of this block.
-//  pass 0: part <- V[:, 0..j]^T w (first classical Gram-Schmidt pass)
-//  pass 1: h = sum(part); alpha_j = h_j; w -= V h; part <- V^T w (second pass)
-//  pass 2: h = sum(part); w -= V h; part <- ||w||^2
-__global__ __launch_bounds__(256) void lz_orth_kernel(const double *V, int64_t n, int j, double *w, const double *part_in,
-                                                      double *part_out, Scalars *scal, int pass) {
+// Orthogonalisation pass of step j over the rows of this block.
+//  pass 1: h = sum(pa); alpha_j = h_j; w -= V h; pb <- V^T w (second GS pass)
+//  pass 2: h = sum(pb); w -= V h; pa <- ||w||^2
+// (the first pass's partials come with the reduction that formed w)
+__global__ __launch_bounds__(256) void lz_orth_kernel(const MatDesc *D, const WorkItem *W, int j, int pass) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    Scalars *scal = dm.scal;
     if (scal->stop) return;
-    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
-    const int nb = gridDim.x;
+    const int b = (int)wi.y;
+    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
+    const double *part_in = pass == 1 ? dm.pa : dm.pb;
+    double *part_out = pass == 1 ? dm.pb : dm.pa;
     __shared__ double hsh[kMaxLanczos];
     __shared__ double red[4 * kMaxLanczos];
-    double wi = (i < n) ? w[i] : 0.0;
-    if (pass > 0) {
-        if (threadIdx.x <= j) hsh[threadIdx.x] = sum_partials(part_in, nb, kMaxLanczos, threadIdx.x);
-        __syncthreads();
-        if (pass == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
-            scal->alpha[j] = hsh[j];
-            scal->amax = fmax(scal->amax, fabs(hsh[j]));
-        }
-        if (i < n) {
-            double s = 0.0;
-            for (int k = 0; k <= j; ++k) s += V[(int64_t)k * n + i] * hsh[k];
-            wi -= s;
-            w[i] = wi;
-        }
+    double wi_ = (i < n) ? dm.w[i] : 0.0;
+    if (threadIdx.x <= j) hsh[threadIdx.x] = sum_partials(part_in, dm.nbv, kMaxLanczos, threadIdx.x);
+    __syncthreads();
+    if (pass == 1 && b == 0 && threadIdx.x == 0) {
+        scal->alpha[j] = hsh[j];
+        scal->amax = fmax(scal->amax, fabs(hsh[j]));
     }
-    if (pass < 2) {
+    if (i < n) {
+        double s = 0.0;
+        for (int k = 0; k <= j; ++k) s += dm.V[(int64_t)k * n + i] * hsh[k];
+        wi_ -= s;
+        dm.w[i] = wi_;
+    }
+    if (pass == 1) {
         double h[kMaxLanczos];
 #pragma unroll
-        for (int k = 0; k < kMaxLanczos; ++k) h[k] = (k <= j && i < n) ? V[(int64_t)k * n + i] * wi : 0.0;
+        for (int k = 0; k < kMaxLanczos; ++k) h[k] = (k <= j && i < n) ? dm.V[(int64_t)k * n + i] * wi_ : 0.0;
         block_reduce<kMaxLanczos>(h, red);
         if (threadIdx.x == 0)
-            for (int k = 0; k <= j; ++k) part_out[(int64_t)blockIdx.x * kMaxLanczos + k] = h[k];
+            for (int k = 0; k <= j; ++k) part_out[(int64_t)b * kMaxLanczos + k] = h[k];
     } else {
-        double x[1] = {wi * wi};
+        double x[1] = {wi_ * wi_};
         block_reduce<1>(x, red);
-        if (threadIdx.x == 0) part_out[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+        if (threadIdx.x == 0) part_out[(int64_t)b * kMaxLanczos] = x[0];
     }
 }
 
-// beta_j = ||w||; stop if beta_j <= 1e-13 max|alpha| or j is the last step,
-// else V[:, j+1] = w / beta_j.
-__global__ __launch_bounds__(256) void lz_next_kernel(double *V, int64_t n, int j, int steps, const double *w,
-                                                      const double *part, Scalars *scal) {
+// beta_j = ||w|| (from pa); stop if beta_j <= 1e-13 max|alpha| or j is the
+// last step, else V[:, j+1] = w / beta_j.
+__global__ __launch_bounds__(256) void lz_next_kernel(const MatDesc *D, const WorkItem *W, int j, int steps) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    Scalars *scal = dm.scal;
     if (scal->stop) return;
-    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
-    const double beta = sqrt(sum_partials(part, gridDim.x, kMaxLanczos, 0));
+    const int b = (int)wi.y;
+    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
+    const double beta = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
     const bool stop = (j == steps - 1) || !(beta > 1e-13 * scal->amax);
-    if (!stop && i < n) V[(int64_t)(j + 1) * n + i] = w[i] / beta;
-    // Every block has read scal->stop/amax above; the flag update below is
-    // seen only by later kernels on the stream.
+    if (!stop && i < n) dm.V[(int64_t)(j + 1) * n + i] = dm.w[i] / beta;
+    // Every block has read scal->stop/amax above; the updates below are seen
+    // only by later kernels on the stream.
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (b == 0 && threadIdx.x == 0) {
         scal->k = j + 1;
         scal->beta_last = beta;
         if (!stop) scal->beta[j] = beta;
+        if (stop) scal->stop = 1;
     }
-    if (stop && blockIdx.x == 0 && threadIdx.x == 0) scal->stop = 1;
 }
 
 // Number of eigenvalues of the k x k symmetric tridiagonal (al, be) below x
@@ -367,7 +363,8 @@ __device__ __forceinline__ int sturm_count(const double *al, const double *be, i
 // T - sigma I with a partially pivoted tridiagonal LU (one thread; loops are
 // unrolled to KM with guards so the arrays stay in registers).
 template <int KM>
-__global__ __launch_bounds__(64) void lz_ritz_kernel(Scalars *scal) {
+__global__ __launch_bounds__(64) void lz_ritz_kernel(const MatDesc *D) {
+    Scalars *scal = D[blockIdx.x].scal;
     const int lane = threadIdx.x;
     const int k = scal->k;
     __shared__ double al[kMaxLanczos], be[kMaxLanczos];
@@ -475,50 +472,59 @@ __global__ __launch_bounds__(64) void lz_ritz_kernel(Scalars *scal) {
     for (int i = 0; i < kMaxLanczos; ++i) scal->s[i] = i < KM ? x[i < KM ? i : 0] * (i < k ? 1.0 : 0.0) : 0.0;
 }
 
-// q = V[:, 0..k) s; part <- ||q||^2
-__global__ __launch_bounds__(256) void lz_q_kernel(const double *V, int64_t n, double *q, double *part, const Scalars *scal) {
-    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+// q = V[:, 0..k) s (into u); pa <- ||q||^2
+__global__ __launch_bounds__(256) void lz_q_kernel(const MatDesc *D, const WorkItem *W) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    const int b = (int)wi.y;
+    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
     __shared__ double red[4];
     double qi = 0.0;
     if (i < n) {
-        for (int k = 0; k < scal->k; ++k) qi += V[(int64_t)k * n + i] * scal->s[k];
-        q[i] = qi;
+        for (int k = 0; k < dm.scal->k; ++k) qi += dm.V[(int64_t)k * n + i] * dm.scal->s[k];
+        dm.u[i] = qi;
     }
     double x[1] = {qi * qi};
     block_reduce<1>(x, red);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+    if (threadIdx.x == 0) dm.pa[(int64_t)b * kMaxLanczos] = x[0];
 }
 
-__global__ void lz_qnorm_kernel(const double *part, int nb, Scalars *scal) {
+__global__ void lz_qnorm_kernel(const MatDesc *D) {
     if (threadIdx.x != 0) return;
-    const double nrm = sqrt(sum_partials(part, nb, kMaxLanczos, 0));
-    scal->qnorm_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    const MatDesc &dm = D[blockIdx.x];
+    const double nrm = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
+    dm.scal->qnorm_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
 }
 
-// part <- ||w - sigma q_hat||^2 with q_hat = q * qnorm_inv
-__global__ __launch_bounds__(256) void lz_resid_kernel(const double *w, const double *q, int64_t n, double *part,
-                                                       const Scalars *scal) {
-    const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
+// pa <- ||w2 - sigma q_hat||^2 with q_hat = u * qnorm_inv
+__global__ __launch_bounds__(256) void lz_resid_kernel(const MatDesc *D, const WorkItem *W) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    const int b = (int)wi.y;
+    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
     __shared__ double red[4];
     double r = 0.0;
-    if (i < n) r = w[i] - scal->sigma * (q[i] * scal->qnorm_inv);
+    if (i < n) r = dm.w2[i] - dm.scal->sigma * (dm.u[i] * dm.scal->qnorm_inv);
     double x[1] = {r * r};
     block_reduce<1>(x, red);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMaxLanczos] = x[0];
+    if (threadIdx.x == 0) dm.pa[(int64_t)b * kMaxLanczos] = x[0];
 }
 
-// Frobenius norm and column-norm maximum from colsq, residual from the
-// partials, then lam = sqrt(sigma + r) (Theorem 2), guarded: if lam is not at
-// least the largest column norm (a lower bound on ||X||_2) the Frobenius norm
-// is used; lam is capped by the Frobenius norm (also an upper bound).
-__global__ __launch_bounds__(256) void lz_bound_kernel(const double *colsq, int64_t n, const double *part, int nb,
-                                                       Scalars *scal, int force_fallback) {
+// Frobenius norm and column-norm maximum from colsq, residual from pa, then
+// lam = sqrt(sigma + r) (Theorem 2), guarded: if lam is not at least the
+// largest column norm (a lower bound on ||X||_2) the Frobenius norm is used;
+// lam is capped by the Frobenius norm (also an upper bound). One block per
+// matrix. A positive override replaces the bound (the norms are kept).
+__global__ __launch_bounds__(256) void lz_bound_kernel(const MatDesc *D, int force_fallback, double lam_override) {
+    const MatDesc &dm = D[blockIdx.x];
+    Scalars *scal = dm.scal;
+    const int64_t n = dm.n;
     __shared__ double sh_sum[256], sh_max[256];
     double s = 0.0, m = 0.0;
     int bad = 0;
     // fixed per-thread stride, then a fixed-order tree: deterministic
     for (int64_t i = threadIdx.x; i < n; i += 256) {
-        const double c = colsq[i];
+        const double c = dm.colsq[i];
         s += c;
         if (!(c <= 1.7e308)) bad = 1;  // NaN or Inf
         m = fmax(m, c);
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(256) void lz_bound_kernel(const double *colsq, int6
     scal->colmax2 = colmax2;
     const int nonfinite = !(fro2 <= 1.7e308) || !(colmax2 <= 1.7e308);
     scal->nonfinite = nonfinite;
-    const double r = sqrt(sum_partials(part, nb, kMaxLanczos, 0));
+    const double r = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
     scal->resid = r;
     const double lz = sqrt(fmax(scal->sigma + r, 0.0));
     scal->lanczos_lam = lz;
@@ -549,88 +555,118 @@ __global__ __launch_bounds__(256) void lz_bound_kernel(const double *colsq, int6
     if (force_fallback) lam = 0.5 * lz;  // test hook: an invalid bound
     if (!(lam >= colmax)) { lam = fro; fb = 1; }
     if (lam > fro) lam = fro;
+    if (lam_override > 0.0) { lam = lam_override; fb = 0; }
     scal->fallback = fb;
     scal->lam = nonfinite ? 0.0 : lam;
     scal->inv_lam = (nonfinite || !(lam > 0.0)) ? 0.0 : 1.0 / lam;
 }
 
-__global__ void scal_init_kernel(Scalars *scal) {
-    if (threadIdx.x == 0) {
-        Scalars z = {};
-        *scal = z;
-    }
-}
-
-hipError_t spectral_bound(const float *X, int64_t ldx, int64_t n, int steps, uint64_t seed, LanczosWork wk,
-                          Scalars *scal, int force_fallback, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int force_fallback, double lam_override,
+                          hipStream_t s) {
     if (steps < 1 || steps > kMaxLanczos) return hipErrorInvalidValue;
-    const unsigned nbv = (unsigned)((n + kRows - 1) / kRows);
-    const int64_t T = (n + kTB - 1) / kTB;
-    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
-    if (nbv == 0) return hipSuccess;
-    double *V = wk.V, *u = wk.u, *w = wk.w, *pa = wk.part_a, *pb = wk.part_b;
-    double *d = wk.sd, *a = wk.sa, *d2 = wk.sd2, *a2 = wk.sa2;
-    const double *nulld = nullptr;
-    // y = X v: tile partials, then the fixed-order reduction (+ first GS pass)
-    auto symv = [&](const double *vin, const double *vscale, double *yout, bool norms, bool orth0, int jstep,
-                    double *part, int stop_flag) {
-        if (norms) {
-            hipLaunchKernelGGL(symv_tile_kernel<true>, dim3(ntiles), dim3(256), 0, s, X, ldx, n, vin, vscale, d, a,
-                               d2, a2, (const Scalars *)scal, stop_flag);
-            hipLaunchKernelGGL((symv_reduce_kernel<true, false>), dim3(nbv), dim3(256), 0, s, n, (const double *)d,
-                               (const double *)a, (const double *)d2, (const double *)a2, yout, wk.colsq, nulld, 0,
-                               (double *)nullptr, (const Scalars *)scal, stop_flag);
-        } else {
-            hipLaunchKernelGGL(symv_tile_kernel<false>, dim3(ntiles), dim3(256), 0, s, X, ldx, n, vin, vscale, d, a,
-                               (double *)nullptr, (double *)nullptr, (const Scalars *)scal, stop_flag);
-            if (orth0)
-                hipLaunchKernelGGL((symv_reduce_kernel<false, true>), dim3(nbv), dim3(256), 0, s, n,
-                                   (const double *)d, (const double *)a, nulld, nulld, yout, (double *)nullptr,
-                                   (const double *)V, jstep, part, (const Scalars *)scal, stop_flag);
-            else
-                hipLaunchKernelGGL((symv_reduce_kernel<false, false>), dim3(nbv), dim3(256), 0, s, n,
-                                   (const double *)d, (const double *)a, nulld, nulld, yout, (double *)nullptr, nulld,
-                                   0, (double *)nullptr, (const Scalars *)scal, stop_flag);
-        }
+    if (B.count == 0) return hipSuccess;
+    const MatDesc *D = B.desc;
+    const unsigned nv = (unsigned)B.n_vec, nt = (unsigned)B.n_symv, M = (unsigned)B.count;
+    const WorkItem *Wv = B.w_vec, *Wt = B.w_symv;
+    auto symv = [&](int src, int jstep, int dst, bool norms, bool orth0, int stop_flag) {
+        if (norms)
+            hipLaunchKernelGGL(symv_tile_kernel<true>, dim3(nt), dim3(256), 0, s, D, Wt, B.io_tab, B.io0, src, jstep,
+                               stop_flag);
+        else
+            hipLaunchKernelGGL(symv_tile_kernel<false>, dim3(nt), dim3(256), 0, s, D, Wt, B.io_tab, B.io0, src, jstep,
+                               stop_flag);
+        if (norms)
+            hipLaunchKernelGGL((symv_reduce_kernel<true, false>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+                               stop_flag);
+        else if (orth0)
+            hipLaunchKernelGGL((symv_reduce_kernel<false, true>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+                               stop_flag);
+        else
+            hipLaunchKernelGGL((symv_reduce_kernel<false, false>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+                               stop_flag);
     };
-    hipLaunchKernelGGL(scal_init_kernel, dim3(1), dim3(64), 0, s, scal);
-    hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 0, seed);
-    hipLaunchKernelGGL(lz_start_kernel, dim3(nbv), dim3(256), 0, s, V, n, pa, 1, seed);
+    hipLaunchKernelGGL(scal_init_kernel, dim3(M), dim3(64), 0, s, D);
+    hipLaunchKernelGGL(lz_start_kernel, dim3(nv), dim3(256), 0, s, D, Wv, 0, seed);
+    hipLaunchKernelGGL(lz_start_kernel, dim3(nv), dim3(256), 0, s, D, Wv, 1, seed);
     for (int j = 0; j < steps; ++j) {
-        symv(V + (int64_t)j * n, nullptr, u, j == 0, false, 0, nullptr, 1);  // u = X v_j
-        symv(u, nullptr, w, false, true, j, pa, 1);                           // w = X u, part_a = V^T w
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pa,
-                           pb, scal, 1);
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, j, w, (const double *)pb,
-                           pa, scal, 2);
-        hipLaunchKernelGGL(lz_next_kernel, dim3(nbv), dim3(256), 0, s, V, n, j, steps, (const double *)w,
-                           (const double *)pa, scal);
+        symv(SRC_V, j, DST_U, j == 0, false, 1);  // u = X v_j (first step: + column norms)
+        symv(SRC_U, j, DST_W, false, true, 1);    // w = X u, pa = V^T w
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, 1);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, 2);
+        hipLaunchKernelGGL(lz_next_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, steps);
     }
     if (steps <= 20)
-        hipLaunchKernelGGL(lz_ritz_kernel<20>, dim3(1), dim3(64), 0, s, scal);
+        hipLaunchKernelGGL(lz_ritz_kernel<20>, dim3(M), dim3(64), 0, s, D);
     else
-        hipLaunchKernelGGL(lz_ritz_kernel<kMaxLanczos>, dim3(1), dim3(64), 0, s, scal);
-    hipLaunchKernelGGL(lz_q_kernel, dim3(nbv), dim3(256), 0, s, (const double *)V, n, u, pa, (const Scalars *)scal);
-    hipLaunchKernelGGL(lz_qnorm_kernel, dim3(1), dim3(64), 0, s, (const double *)pa, (int)nbv, scal);
-    symv(u, &scal->qnorm_inv, w, false, false, 0, nullptr, 0);  // X q_hat
-    symv(w, nullptr, wk.w2, false, false, 0, nullptr, 0);       // X^2 q_hat
-    hipLaunchKernelGGL(lz_resid_kernel, dim3(nbv), dim3(256), 0, s, (const double *)wk.w2, (const double *)u, n, pa,
-                       (const Scalars *)scal);
-    hipLaunchKernelGGL(lz_bound_kernel, dim3(1), dim3(256), 0, s, (const double *)wk.colsq, n, (const double *)pa,
-                       (int)nbv, scal, force_fallback);
+        hipLaunchKernelGGL(lz_ritz_kernel<kMaxLanczos>, dim3(M), dim3(64), 0, s, D);
+    hipLaunchKernelGGL(lz_q_kernel, dim3(nv), dim3(256), 0, s, D, Wv);
+    hipLaunchKernelGGL(lz_qnorm_kernel, dim3(M), dim3(64), 0, s, D);
+    symv(SRC_QHAT, 0, DST_W, false, false, 0);  // w = X q_hat
+    symv(SRC_W, 0, DST_W2, false, false, 0);    // w2 = X^2 q_hat
+    hipLaunchKernelGGL(lz_resid_kernel, dim3(nv), dim3(256), 0, s, D, Wv);
+    hipLaunchKernelGGL(lz_bound_kernel, dim3(M), dim3(256), 0, s, D, force_fallback, lam_override);
+    return hipGetLastError();
+}
+
+hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, hipStream_t s) {
+    if (B.count == 0 || B.n_cast == 0) return hipSuccess;
+    const dim3 g((unsigned)B.n_cast), blk(256);
+    switch (dtype) {
+        case 0: hipLaunchKernelGGL((cast_kernel<float, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+            break;
+        case 1:
+            if (split)
+                hipLaunchKernelGGL((cast_kernel<f16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 2048.0f);
+            else
+                hipLaunchKernelGGL((cast_kernel<f16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+            break;
+        case 2:
+            if (split)
+                hipLaunchKernelGGL((cast_kernel<bf16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+            else
+                hipLaunchKernelGGL((cast_kernel<bf16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 size_t lanczos_work_doubles(int64_t n, int steps) {
     const int64_t nbv = (n + kRows - 1) / kRows;
-    const int64_t T = (n + kTB - 1) / kTB;
-    const int64_t tiles = T * (T + 1) / 2;
+    const int64_t tiles = symv_tile_count(n);
     return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + 4 * tiles * kTB + 64);
 }
 
 int64_t symv_tile_count(int64_t n) {
     const int64_t T = (n + kTB - 1) / kTB;
     return T * (T + 1) / 2;
+}
+
+int64_t vec_block_count(int64_t n) { return (n + kRows - 1) / kRows; }
+
+int64_t cast_tile_count(int64_t np) {
+    const int64_t T = (np + 63) / 64;
+    return T * (T + 1) / 2;
+}
+
+void fill_lanczos_desc(MatDesc &d, double *lz, int64_t n, int steps) {
+    const int64_t nbv = vec_block_count(n);
+    const int64_t tiles = symv_tile_count(n);
+    d.nbv = (int32_t)nbv;
+    d.V = lz;
+    d.u = d.V + n * steps;
+    d.w = d.u + n;
+    d.w2 = d.w + n;
+    d.colsq = d.w2 + n;
+    d.pa = d.colsq + n;
+    d.pb = d.pa + nbv * kMaxLanczos;
+    d.sd = d.pb + nbv * kMaxLanczos;
+    d.sa = d.sd + tiles * kTB;
+    d.sd2 = d.sa + tiles * kTB;
+    d.sa2 = d.sd2 + tiles * kTB;
 }
 
 }  // namespace psd

@@ -4,25 +4,30 @@
 
 namespace psd {
 
-struct LanczosWork {
-    double *V;      // n x steps, column-major
-    double *u, *w, *w2, *colsq;  // n each
-    double *part_a, *part_b;     // per-block partials, nb x 32 each
-    double *sd, *sa, *sd2, *sa2; // symmetric-matvec tile partials, tiles x 128 each
+// Device tables of one batched launch: descriptors, caller I/O (io_tab, or
+// io0 by value for a single matrix) and the work lists of each grid shape.
+struct BatchLaunch {
+    int count = 0;                 // matrices
+    const MatDesc *desc = nullptr; // device, count entries
+    const IoArg *io_tab = nullptr; // device, count entries (nullptr: use io0)
+    IoArg io0{};
+    const WorkItem *w_vec = nullptr;   // (m, block of 256 rows)
+    const WorkItem *w_symv = nullptr;  // (m, 128 x 128 triangle tile)
+    const WorkItem *w_cast = nullptr;  // (m, 64 x 64 tile pair of the padded matrix)
+    int64_t n_vec = 0, n_symv = 0, n_cast = 0;
 };
 
-// O = scale * sym(X), scale = 1 or scal->inv_lam; dtype 0 FP32, 1 FP16, 2 BF16;
-// Olo != nullptr writes a hi + lo pair. n_out (multiple of 64) >= n: entries
-// outside n x n are zero.
-hipError_t mirror_cast(const float *X, int64_t ldx, int64_t n, int64_t n_out, const Scalars *scal, int use_inv_lam,
-                       int dtype, void *Ohi, void *Olo, int64_t ldo, hipStream_t s);
-
-// Lanczos bound of the symmetric matrix whose upper triangle X holds
-// (FP32, column-major, leading dimension ldx) into scal.
-hipError_t spectral_bound(const float *X, int64_t ldx, int64_t n, int steps, uint64_t seed, LanczosWork wk,
-                          Scalars *scal, int force_fallback, hipStream_t s);
+// Lanczos bound (Theorem 2) of every matrix into its Scalars.
+hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int force_fallback, double lam_override,
+                          hipStream_t s);
+// Slot 0 <- X / lam in dtype (0 FP32, 1 FP16, 2 BF16), optionally hi + lo.
+hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, hipStream_t s);
 
 size_t lanczos_work_doubles(int64_t n, int steps);
 int64_t symv_tile_count(int64_t n);
+int64_t vec_block_count(int64_t n);
+int64_t cast_tile_count(int64_t np);
+// Lanczos pointers of a descriptor inside lz (lanczos_work_doubles doubles).
+void fill_lanczos_desc(MatDesc &d, double *lz, int64_t n, int steps);
 
 }  // namespace psd

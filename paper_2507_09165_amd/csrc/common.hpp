@@ -38,6 +38,34 @@ struct Scalars {
 
 constexpr int kMaxLanczos = 32;
 
+// Per-matrix descriptor of one projection's device workspace. A launch covers
+// every matrix of a batch: its work list maps each workgroup to a
+// (matrix, local block) pair and the kernel reads the matrix's descriptor.
+struct MatDesc {
+    int64_t n;        // matrix order
+    int64_t np;       // padded order of the work matrices (GEMM tile multiple)
+    int64_t ldw;      // leading dimension of the work matrices (>= np)
+    Scalars *scal;
+    // Lanczos work: V (n x steps), vectors (n), partials (nbv x 32), symv tile partials (tiles x 128)
+    double *V, *u, *w, *w2, *colsq, *pa, *pb, *sd, *sa, *sd2, *sa2;
+    void *hi[4], *lo[4];  // work slots: X0, then rotating A / B / X_t
+    int32_t nbv;          // vector blocks: ceil(n / 256)
+    int32_t pad_;
+};
+
+// Caller-owned input and output of one matrix: X upper triangle and out,
+// FP32 column-major with leading dimension ld.
+struct IoArg {
+    const float *X;
+    float *out;
+    int64_t ld;
+};
+
+// (matrix, local block) pair of a work list.
+typedef uint2 WorkItem;
+
+__device__ __forceinline__ IoArg io_of(const IoArg *tab, const IoArg &io0, int m) { return tab ? tab[m] : io0; }
+
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 }  // namespace psd

@@ -117,8 +117,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     static_assert(NST >= 2, "at least two LDS stages");
     __shared__ __attribute__((aligned(16))) uint8_t smem[NST * STAGE];
 
-    const uint32_t tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const int bi = (int)(tv & 0xFFFFu), bj = (int)(tv >> 16);
+    const WorkItem tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const MatDesc &dm = g.D[tv.x];
+    const int bi = (int)(tv.y & 0xFFFFu), bj = (int)(tv.y >> 16);
     const int64_t i0 = (int64_t)bi * BM;
     const int64_t j0 = (int64_t)bj * BM;
     const int tid = threadIdx.x;
@@ -126,16 +127,16 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     const int wave = tid >> 6;
     const int wr = (wave >> 1) * WM;
     const int wc = (wave & 1) * WM;
-    const int64_t ld = g.ld;
+    const int64_t ld = dm.ldw;
 
     // Operand panels of one K-tile, in LDS order: L_hi, [L_lo], R_hi, [R_lo].
     const uint8_t *src[4];
     {
         int p = 0;
-        src[p++] = (const uint8_t *)g.Lhi;
-        if constexpr (LS) src[p++] = (const uint8_t *)g.Llo;
-        src[p++] = (const uint8_t *)g.Rhi;
-        if constexpr (RS) src[p++] = (const uint8_t *)g.Rlo;
+        src[p++] = (const uint8_t *)dm.hi[g.sl];
+        if constexpr (LS) src[p++] = (const uint8_t *)dm.lo[g.sl];
+        src[p++] = (const uint8_t *)dm.hi[g.sr];
+        if constexpr (RS) src[p++] = (const uint8_t *)dm.lo[g.sr];
     }
     // Direct global->LDS loads: one wave instruction moves 64 x 16 bytes into
     // 1 KB of contiguous LDS (lane l -> byte 16 l). The K-tile of all panels
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         key_b[m] = swz<NCH>(rb, 0);
     }
 
-    const int64_t nk = g.K / BK;
+    const int64_t nk = dm.np / BK;
     // Fragments of one K-substep: operand panel p, MFMA block m.
     typedef u32x4 Frag[NLP + NRP][MI];
     auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
@@ -257,9 +258,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     const float acc_scale = (LS || RS) ? 1.0f / Elt<T>::kSplit : 1.0f;
     const bool diag = (bi == bj);
     if constexpr (EPI == EPI_FINAL) {
-        if (g.scal->nonfinite) return;  // leave the output untouched
-        const float hl = 0.5f * (float)g.scal->lam * acc_scale;
-        const int64_t n = g.n;
+        if (dm.scal->nonfinite) return;  // leave the output untouched
+        const IoArg io = io_of(g.io_tab, g.io0, tv.x);
+        const float hl = 0.5f * (float)dm.scal->lam * acc_scale;
+        const int64_t n = dm.n;
 #pragma clang loop unroll(full)
         for (int mi = 0; mi < MI; ++mi)
 #pragma clang loop unroll(full)
@@ -275,16 +277,16 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         if (i >= n || (diag && i > j)) continue;
                         // upper-triangle entry (i <= j): read then written by
                         // this thread only, so out == X is safe
-                        const float v = 0.5f * g.Xin[j * g.ldx + i] + hl * acc[mi][ni][4 * eg + q];
-                        g.out[j * g.ldo + i] = v;
-                        g.out[i * g.ldo + j] = v;
+                        const float v = 0.5f * io.X[j * io.ld + i] + hl * acc[mi][ni][4 * eg + q];
+                        io.out[j * io.ld + i] = v;
+                        io.out[i * io.ld + j] = v;
                     }
                 }
     } else {
-        T *Dhi = (T *)g.Dhi;
-        T *Dlo = (T *)g.Dlo;
-        const T *C0hi = (const T *)g.C0hi;
-        const T *C0lo = (const T *)g.C0lo;
+        T *Dhi = (T *)dm.hi[g.sd];
+        T *Dlo = (T *)dm.lo[g.sd];
+        const T *C0hi = g.sc0 >= 0 ? (const T *)dm.hi[g.sc0] : nullptr;
+        const T *C0lo = (g.sc0 >= 0 && g.c0_split) ? (const T *)dm.lo[g.sc0] : nullptr;
         const float c0lo = 1.0f / Elt<T>::kSplit;
         typedef T t4 __attribute__((ext_vector_type(4)));
 #pragma clang loop unroll(full)
@@ -347,46 +349,39 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 // ~32 tiles resident on one XCD at a time form a compact 2D block that shares
 // H + W operand panels in its L2 instead of one panel per tile.
 static int g_tile_override = 0;  // tuning hook: force a tile edge (0 = automatic)
-static int g_block_h = 4, g_block_w = 8;
+static int g_block_h = 4, g_block_w = 4;
+static std::mutex g_cfg_mu;
 
-std::vector<uint32_t> make_tile_order(int T, int H, int W) {
-    std::vector<uint32_t> v;
-    v.reserve((size_t)T * (T + 1) / 2);
+void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T) {
+    int H, W;
+    {
+        std::lock_guard<std::mutex> lk(g_cfg_mu);
+        H = g_block_h;
+        W = g_block_w;
+    }
     for (int s0 = 0; s0 < T; s0 += H)
         for (int c0 = s0; c0 < T; c0 += W)
             for (int bj = c0; bj < std::min(c0 + W, T); ++bj)
                 for (int bi = s0; bi < std::min(s0 + H, T); ++bi)
-                    if (bi <= bj) v.push_back((uint32_t)bi | ((uint32_t)bj << 16));
-    return v;
-}
-
-static std::mutex g_tiles_mu;
-static std::map<std::tuple<int, int, int, int, int>, uint32_t *> g_tiles;
-
-// Device copy of the tile list for (device, T, H, W); built once (the first
-// use synchronises the device for the upload).
-static const uint32_t *tile_list(int T, hipError_t *err) {
-    int dev = 0;
-    *err = hipGetDevice(&dev);
-    if (*err != hipSuccess) return nullptr;
-    const auto key = std::make_tuple(dev, T, g_block_h, g_block_w, 0);
-    std::lock_guard<std::mutex> lk(g_tiles_mu);
-    auto it = g_tiles.find(key);
-    if (it != g_tiles.end()) return it->second;
-    const std::vector<uint32_t> v = make_tile_order(T, g_block_h, g_block_w);
-    uint32_t *d = nullptr;
-    *err = hipMalloc(&d, v.size() * sizeof(uint32_t));
-    if (*err != hipSuccess) return nullptr;
-    *err = hipMemcpy(d, v.data(), v.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (*err != hipSuccess) { (void)hipFree(d); return nullptr; }
-    g_tiles[key] = d;
-    return d;
+                    if (bi <= bj) v.push_back(WorkItem{m, (uint32_t)bi | ((uint32_t)bj << 16)});
 }
 
 int gemm_pick_tile(int64_t K) {
-    if (g_tile_override && K % g_tile_override == 0) return g_tile_override;
-    if (K % 256 == 0 && K >= 2048) return 256;
+    const int o = g_tile_override;
+    if (o && K % o == 0) return o;
+    if (K % 256 == 0 && K >= 1536) return 256;
     return 128;
+}
+
+// Padded order of the work matrices: a multiple of the tile the launcher will
+// pick for it (the override, else 256 from n = 1536 on, else 128). Any choice
+// gives bitwise-identical results: every element accumulates its K products
+// in the same order whatever the tile shape, and padding only adds zeros.
+int64_t gemm_padded_size(int64_t n) {
+    const int64_t m = n > 0 ? n : 1;
+    const int o = g_tile_override;
+    if (o) return round_up(m, o);
+    return m >= 1536 ? round_up(m, 256) : round_up(m, kTile);
 }
 
 // LDS configuration per (tile, operand panels): the 128 tile keeps two
@@ -399,65 +394,59 @@ template <int BM, int NP> struct LdsCfg {
 };
 
 template <typename T, bool LS, bool RS, int EPI, int BM>
-static hipError_t launch_bm(const GemmArgs &g, hipStream_t s) {
+static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s) {
     constexpr int NP = 2 + (LS ? 1 : 0) + (RS ? 1 : 0);
     constexpr int ROWB = LdsCfg<BM, NP>::ROWB;
     constexpr int NST = LdsCfg<BM, NP>::NST;
-    const int T_ = (int)(g.K / BM);
-    const int ntiles = T_ * (T_ + 1) / 2;
     if (ntiles == 0) return hipSuccess;
-    hipError_t err;
-    GemmArgs a = g;
-    a.tiles = tile_list(T_, &err);
-    if (!a.tiles) return err;
-    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST>), dim3(ntiles), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST>), dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                       g);
     return hipGetLastError();
 }
 
 template <typename T, bool LS, bool RS, int EPI>
-static hipError_t launch_t(const GemmArgs &g, hipStream_t s) {
-    switch (gemm_pick_tile(g.K)) {
-        case 256: return launch_bm<T, LS, RS, EPI, 256>(g, s);
-        case 128: return launch_bm<T, LS, RS, EPI, 128>(g, s);
+static hipError_t launch_t(const GemmArgs &g, int bm, int64_t ntiles, hipStream_t s) {
+    switch (bm) {
+        case 256: return launch_bm<T, LS, RS, EPI, 256>(g, ntiles, s);
+        case 128: return launch_bm<T, LS, RS, EPI, 128>(g, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T, int EPI>
-static hipError_t launch_split(const GemmArgs &g, hipStream_t s) {
-    const bool ls = g.Llo != nullptr, rs = g.Rlo != nullptr;
-    if (ls && rs) return launch_t<T, true, true, EPI>(g, s);
-    if (ls) return launch_t<T, true, false, EPI>(g, s);
-    if (rs) return launch_t<T, false, true, EPI>(g, s);
-    return launch_t<T, false, false, EPI>(g, s);
+static hipError_t launch_split(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s) {
+    if (ls && rs) return launch_t<T, true, true, EPI>(g, bm, ntiles, s);
+    if (ls) return launch_t<T, true, false, EPI>(g, bm, ntiles, s);
+    if (rs) return launch_t<T, false, true, EPI>(g, bm, ntiles, s);
+    return launch_t<T, false, false, EPI>(g, bm, ntiles, s);
 }
 
 template <typename T>
-static hipError_t launch_epi(const GemmArgs &g, int epi, hipStream_t s) {
+static hipError_t launch_epi(const GemmArgs &g, int epi, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s) {
     switch (epi) {
-        case EPI_STORE: return launch_split<T, EPI_STORE>(g, s);
-        case EPI_STORE_SPLIT: return launch_split<T, EPI_STORE_SPLIT>(g, s);
-        case EPI_FINAL: return launch_split<T, EPI_FINAL>(g, s);
+        case EPI_STORE: return launch_split<T, EPI_STORE>(g, ls, rs, bm, ntiles, s);
+        case EPI_STORE_SPLIT: return launch_split<T, EPI_STORE_SPLIT>(g, ls, rs, bm, ntiles, s);
+        case EPI_FINAL: return launch_split<T, EPI_FINAL>(g, ls, rs, bm, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, hipStream_t s) {
-    if (g.K % kTile) return hipErrorInvalidValue;
+hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool rs, int bm, int64_t ntiles,
+                           hipStream_t s) {
     switch (dtype) {
         case DT_F32:
-            if (g.Llo || g.Rlo || epi == EPI_STORE_SPLIT) return hipErrorInvalidValue;
-            return epi == EPI_STORE ? launch_t<float, false, false, EPI_STORE>(g, s)
-                                    : launch_t<float, false, false, EPI_FINAL>(g, s);
-        case DT_F16: return launch_epi<f16>(g, epi, s);
-        case DT_BF16: return launch_epi<bf16>(g, epi, s);
+            if (ls || rs || epi == EPI_STORE_SPLIT) return hipErrorInvalidValue;
+            return epi == EPI_STORE ? launch_t<float, false, false, EPI_STORE>(g, bm, ntiles, s)
+                                    : launch_t<float, false, false, EPI_FINAL>(g, bm, ntiles, s);
+        case DT_F16: return launch_epi<f16>(g, epi, ls, rs, bm, ntiles, s);
+        case DT_BF16: return launch_epi<bf16>(g, epi, ls, rs, bm, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
 
 void gemm_set_tile_override(int bm) { g_tile_override = bm; }
 void gemm_set_block_shape(int h, int w) {
-    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
     g_block_h = h;
     g_block_w = w;
 }

@@ -1,5 +1,7 @@
 // Host interface of the symmetric MFMA GEMM (see gemm_sym.hip).
 #pragma once
+#include <vector>
+
 #include "common.hpp"
 
 namespace psd {
@@ -10,35 +12,31 @@ enum Epi { EPI_STORE = 0, EPI_STORE_SPLIT = 1, EPI_FINAL = 2 };
 // Output tile edge; work matrices are zero-padded to a multiple of it.
 constexpr int kTile = 128;
 
+// One symmetric product D = alpha C0 + beta (L R) + gamma I for every matrix
+// named by the tile list. Operands, addend and output are work slots of the
+// matrix's descriptor (hi[slot], lo[slot]); sc0 < 0 means no addend. The
+// final epilogue instead writes out = (X + lam L R) / 2 to the caller's I/O.
 struct GemmArgs {
-    // Operands (n_p x n_p, column-major, leading dimension ld, symmetric).
-    // *lo == nullptr means the operand is a single (unsplit) matrix.
-    const void *Lhi, *Llo, *Rhi, *Rlo;
-    // Epilogue addend C0 (same layout; may be nullptr) and outputs.
-    const void *C0hi, *C0lo;
-    void *Dhi, *Dlo;
-    // Final epilogue: out (FP32, n x n, ldo) = (X + lam * acc) / 2, X read from
-    // its upper triangle (Xin, column-major, leading dimension ldx).
-    float *out;
-    int64_t ldo;
-    int64_t n;
-    const float *Xin;
-    int64_t ldx;
-    const Scalars *scal;
-    const uint32_t *tiles;  // filled by the launcher: tile list (bi | bj << 16)
-    int64_t ld;  // leading dimension of the work matrices
-    int64_t K;   // padded size n_p (multiple of kTile)
-    float alpha, beta, gamma;  // D = alpha C0 + beta (L R) + gamma I
+    const MatDesc *D;
+    const WorkItem *tiles;  // (matrix, bi | bj << 16), upper tiles only
+    const IoArg *io_tab;    // final epilogue: per-matrix I/O, or
+    IoArg io0;              // the single matrix's I/O when io_tab is null
+    int sl, sr, sc0, sd;
+    int c0_split;
+    float alpha, beta, gamma;
 };
 
-hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, hipStream_t s);
+// ls / rs: L / R carry lo halves. bm: tile edge (128 or 256; it must divide
+// every listed matrix's np). ntiles: length of the tile list.
+hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool rs, int bm, int64_t ntiles,
+                           hipStream_t s);
+// Append matrix m's upper tiles (T x T tile grid) in the blocked schedule order.
+void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T);
 
 // Tile edge the launcher uses for a padded size K, and the padded size used for
 // a logical size n (a multiple of the tile it will run with).
 int gemm_pick_tile(int64_t K);
-inline int64_t gemm_padded_size(int64_t n) {
-    return n >= 1536 ? round_up(n, 256) : round_up(n > 0 ? n : 1, kTile);
-}
+int64_t gemm_padded_size(int64_t n);
 // Tuning hook: force the tile edge (0 restores the automatic choice).
 void gemm_set_tile_override(int bm);
 // Tuning hook: blocking of the tile schedule (H tile rows x W tile columns).

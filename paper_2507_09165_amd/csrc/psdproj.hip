@@ -1,9 +1,16 @@
-// C ABI of libpsdproj: argument checks, workspace pool, and the launch
+// C ABI of libpsdproj: argument checks, plans and workspaces, and the launch
 // sequence of Algorithm 2 (bound -> rescale/cast -> T filter stages -> final).
+//
+// A plan covers one call shape — a mode and a list of matrix orders — on one
+// (device, stream). It lays out one arena (from the per-stream workspace
+// pool): the descriptor table, the I/O table, the work lists of every grid
+// shape, and each matrix's workspace. Every kernel launch of the sequence
+// covers all matrices of the plan; a single projection is a plan of one.
 #include <math.h>
 #include <string.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -45,6 +52,8 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
             tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_F16; break;
         case PSDPROJ_MODE_BF16:
             tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_BF16; break;
+        case PSDPROJ_MODE_FP32_EMU:
+            tab = kTildeSingle; T = 10; nres = kSingleRescaled; res = kSingleRescale; p.dtype = DT_F16; break;
         default: return false;
     }
     p.T = T;
@@ -57,47 +66,151 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
     if (o.mode == PSDPROJ_MODE_FP16_SPLIT) {
         p.split_mask = (o.split_mask ? o.split_mask : kDefaultSplitMask) & ((1u << T) - 1);
         p.split_final = o.split_final < 0 ? kDefaultSplitFinal : o.split_final != 0;
+    } else if (o.mode == PSDPROJ_MODE_FP32_EMU) {
+        // every product on hi + lo FP16 pairs: ~22-bit operands, FP32 accumulation
+        p.split_mask = (1u << T) - 1;
+        p.split_final = true;
     }
     return true;
 }
 
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
-struct Layout {
+size_t align256(size_t b) { return (size_t)round_up((int64_t)b, 256); }
+
+// One matrix's workspace inside the arena.
+struct MatLayout {
     int64_t n, np;
-    int steps;
-    bool split;
     size_t off_scal, off_lz, off_mat, mat_bytes, total;
 };
 
-Layout make_layout(int64_t n, const StagePlan &p, int steps) {
-    Layout L{};
+MatLayout mat_layout(int64_t n, const StagePlan &p, int steps) {
+    MatLayout L{};
     L.n = n;
     L.np = gemm_padded_size(n);
-    L.steps = steps;
-    L.split = p.split_mask != 0 || p.split_final;
+    const bool split = p.split_mask != 0 || p.split_final;
     size_t off = 0;
-    auto take = [&](size_t bytes) { const size_t o = off; off += round_up((int64_t)bytes, 256); return o; };
+    auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     L.off_scal = take(sizeof(Scalars));
     L.off_lz = take(sizeof(double) * lanczos_work_doubles(n, steps));
-    L.mat_bytes = round_up((int64_t)(elt_size(p.dtype) * (size_t)L.np * (size_t)L.np), 256);
-    L.off_mat = take(L.mat_bytes * 4 * (L.split ? 2 : 1));
+    L.mat_bytes = align256(elt_size(p.dtype) * (size_t)L.np * (size_t)L.np);
+    L.off_mat = take(L.mat_bytes * 4 * (split ? 2 : 1));
     L.total = off;
     return L;
 }
 
+struct Plan {
+    // key
+    int mode = -1, steps = 0, split_final = 0;
+    uint32_t split_mask = 0;
+    std::vector<int64_t> ns;
+    // layout
+    StagePlan sp;
+    size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[2] = {0, 0}, total = 0;
+    int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[2] = {0, 0};
+    int gemm_bm[2] = {256, 128};
+    std::vector<size_t> mat_off;
+    std::vector<MatLayout> mats;
+    // arena the device tables were built for
+    void *base = nullptr;
+    // pinned staging of the per-call I/O table (multi-matrix plans)
+    IoArg *io_host = nullptr;
+    hipEvent_t io_done = nullptr;
+
+    ~Plan() {
+        if (io_done) (void)hipEventDestroy(io_done);
+        if (io_host) (void)hipHostFree(io_host);
+    }
+    // rq: the stage plan of the request (mode, split choices)
+    bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n) const {
+        return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
+               ns == n;
+    }
+};
+
+void layout_plan(Plan &P) {
+    const size_t M = P.ns.size();
+    P.mats.clear();
+    P.mat_off.clear();
+    P.n_vec = P.n_symv = P.n_cast = 0;
+    P.n_gemm[0] = P.n_gemm[1] = 0;
+    for (int64_t n : P.ns) {
+        P.mats.push_back(mat_layout(n, P.sp, P.steps));
+        const MatLayout &L = P.mats.back();
+        P.n_vec += vec_block_count(n);
+        P.n_symv += symv_tile_count(n);
+        P.n_cast += cast_tile_count(L.np);
+        const int bm = gemm_pick_tile(L.np);
+        const int64_t T = L.np / bm;
+        P.n_gemm[bm == 256 ? 0 : 1] += T * (T + 1) / 2;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+    P.off_desc = take(sizeof(MatDesc) * M);
+    P.off_io = take(sizeof(IoArg) * M);
+    P.off_wvec = take(sizeof(WorkItem) * (size_t)P.n_vec);
+    P.off_wsymv = take(sizeof(WorkItem) * (size_t)P.n_symv);
+    P.off_wcast = take(sizeof(WorkItem) * (size_t)P.n_cast);
+    P.off_wgemm[0] = take(sizeof(WorkItem) * (size_t)P.n_gemm[0]);
+    P.off_wgemm[1] = take(sizeof(WorkItem) * (size_t)P.n_gemm[1]);
+    for (const MatLayout &L : P.mats) P.mat_off.push_back(take(L.total));
+    P.total = off;
+}
+
+// Fill and upload the descriptor table and work lists for arena `base`. The
+// stream is synchronised first: earlier work queued on it may still read the
+// tables being replaced.
+int build_tables(Plan &P, void *base, hipStream_t s) {
+    const size_t M = P.ns.size();
+    uint8_t *b = (uint8_t *)base;
+    std::vector<MatDesc> desc(M);
+    std::vector<WorkItem> wv, wt, wc, wg[2];
+    const bool split = P.sp.split_mask != 0 || P.sp.split_final;
+    for (size_t m = 0; m < M; ++m) {
+        const MatLayout &L = P.mats[m];
+        uint8_t *mb = b + P.mat_off[m];
+        MatDesc &d = desc[m];
+        memset(&d, 0, sizeof(d));
+        d.n = L.n;
+        d.np = L.np;
+        d.ldw = L.np;
+        d.scal = (Scalars *)(mb + L.off_scal);
+        fill_lanczos_desc(d, (double *)(mb + L.off_lz), L.n, P.steps);
+        for (int k = 0; k < 4; ++k) {
+            d.hi[k] = mb + L.off_mat + (size_t)k * L.mat_bytes;
+            d.lo[k] = split ? mb + L.off_mat + (size_t)(4 + k) * L.mat_bytes : nullptr;
+        }
+        for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
+        for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
+        for (int64_t i = 0; i < cast_tile_count(L.np); ++i) wc.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
+        const int bm = gemm_pick_tile(L.np);
+        append_tile_order(wg[bm == 256 ? 0 : 1], (uint32_t)m, (int)(L.np / bm));
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return bytes == 0 || hipMemcpy(b + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(P.off_desc, desc.data(), sizeof(MatDesc) * M) || !up(P.off_wvec, wv.data(), sizeof(WorkItem) * wv.size()) ||
+        !up(P.off_wsymv, wt.data(), sizeof(WorkItem) * wt.size()) ||
+        !up(P.off_wcast, wc.data(), sizeof(WorkItem) * wc.size()) ||
+        !up(P.off_wgemm[0], wg[0].data(), sizeof(WorkItem) * wg[0].size()) ||
+        !up(P.off_wgemm[1], wg[1].data(), sizeof(WorkItem) * wg[1].size()))
+        return PSDPROJ_ERR_HIP;
+    P.base = base;
+    return PSDPROJ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-(device, stream) workspace pool and current plan
 struct Pool {
     void *ptr = nullptr;
     size_t bytes = 0;
+    std::unique_ptr<Plan> plan;
 };
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Pool> g_pool;
 
-int get_workspace(hipStream_t s, size_t bytes, void **out) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
-    std::lock_guard<std::mutex> lk(g_mu);
-    Pool &p = g_pool[{dev, s}];
+int get_workspace(Pool &p, hipStream_t s, size_t bytes, void **out) {
     if (p.bytes < bytes) {
         if (p.ptr) {
             if (hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
@@ -117,8 +230,9 @@ int get_workspace(hipStream_t s, size_t bytes, void **out) {
     return PSDPROJ_OK;
 }
 
-__global__ void info_kernel(const Scalars *s, psdproj_info *info, int stages) {
+__global__ void info_kernel(const MatDesc *D, psdproj_info *info, int stages) {
     if (threadIdx.x != 0) return;
+    const Scalars *s = D[0].scal;
     info->lambda = s->lam;
     info->lanczos_lambda = s->lanczos_lam;
     info->sigma = s->sigma;
@@ -131,88 +245,68 @@ __global__ void info_kernel(const Scalars *s, psdproj_info *info, int stages) {
     info->stages = stages;
 }
 
-// Replace the Lanczos bound by a caller-supplied one (keeps the norms).
-__global__ void override_kernel(Scalars *s, double lam) {
-    if (threadIdx.x != 0) return;
-    s->lam = s->nonfinite ? 0.0 : lam;
-    s->inv_lam = (s->nonfinite || !(lam > 0.0)) ? 0.0 : 1.0 / lam;
-    s->fallback = 0;
-}
-
-struct Mat {
-    void *hi = nullptr, *lo = nullptr;
-};
-
-}  // namespace
-
-int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
-                   psdproj_info *info, bool bound_only) {
-    StagePlan p;
-    if (!make_stage_plan(o, p)) return PSDPROJ_ERR_INVALID_ARG;
-    const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
-    if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
-    if (n < 0 || ld < (n > 1 ? n : 1)) return PSDPROJ_ERR_INVALID_ARG;
-    if (n == 0) return PSDPROJ_OK;
-    if (!X || (!out && !bound_only)) return PSDPROJ_ERR_INVALID_ARG;
-    if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
-
-    const Layout L = make_layout(n, p, steps);
-    void *base = nullptr;
-    int st = get_workspace(s, L.total, &base);
-    if (st != PSDPROJ_OK) return st;
-    uint8_t *b = (uint8_t *)base;
-    Scalars *scal = (Scalars *)(b + L.off_scal);
-    double *lz = (double *)(b + L.off_lz);
-    LanczosWork wk;
-    {
-        const int64_t nbv = (n + 255) / 256;
-        const int64_t tiles = symv_tile_count(n);
-        wk.V = lz;
-        wk.u = wk.V + n * steps;
-        wk.w = wk.u + n;
-        wk.w2 = wk.w + n;
-        wk.colsq = wk.w2 + n;
-        wk.part_a = wk.colsq + n;
-        wk.part_b = wk.part_a + nbv * kMaxLanczos;
-        wk.sd = wk.part_b + nbv * kMaxLanczos;
-        wk.sa = wk.sd + tiles * 128;
-        wk.sd2 = wk.sa + tiles * 128;
-        wk.sa2 = wk.sd2 + tiles * 128;
+// Enqueue the whole sequence for the plan's matrices. ios: host array of the
+// caller's I/O, one per matrix.
+int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, psdproj_info *info, bool bound_only) {
+    uint8_t *b = (uint8_t *)P.base;
+    const int M = (int)P.ns.size();
+    BatchLaunch B;
+    B.count = M;
+    B.desc = (const MatDesc *)(b + P.off_desc);
+    B.w_vec = (const WorkItem *)(b + P.off_wvec);
+    B.w_symv = (const WorkItem *)(b + P.off_wsymv);
+    B.w_cast = (const WorkItem *)(b + P.off_wcast);
+    B.n_vec = P.n_vec;
+    B.n_symv = P.n_symv;
+    B.n_cast = P.n_cast;
+    if (M == 1) {
+        B.io_tab = nullptr;
+        B.io0 = ios[0];
+    } else {
+        // per-call I/O table: pinned staging, reused once its last upload ran
+        if (!P.io_host) {
+            if (hipHostMalloc((void **)&P.io_host, sizeof(IoArg) * M, hipHostMallocDefault) != hipSuccess)
+                return PSDPROJ_ERR_NO_MEMORY;
+            if (hipEventCreateWithFlags(&P.io_done, hipEventDisableTiming) != hipSuccess) return PSDPROJ_ERR_HIP;
+        } else if (hipEventSynchronize(P.io_done) != hipSuccess) {
+            return PSDPROJ_ERR_HIP;
+        }
+        memcpy(P.io_host, ios, sizeof(IoArg) * M);
+        IoArg *io_dev = (IoArg *)(b + P.off_io);
+        if (hipMemcpyAsync(io_dev, P.io_host, sizeof(IoArg) * M, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipEventRecord(P.io_done, s) != hipSuccess)
+            return PSDPROJ_ERR_HIP;
+        B.io_tab = io_dev;
     }
-    hipError_t e;
-    // 1-2. spectral bound (Theorem 2) + guard, from the upper triangle of X
-    e = spectral_bound(X, ld, n, steps, kLanczosSeed, wk, scal, o.force_bound_fallback, s);
+    hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (o.lambda_override > 0.0) hipLaunchKernelGGL(override_kernel, dim3(1), dim3(64), 0, s, scal, o.lambda_override);
     if (bound_only) {
-        if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, (const Scalars *)scal, info, 0);
+        if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, B.desc, info, 0);
         return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
     }
-
-    // 3. work matrices: slot 0 holds X0, slots 1..3 rotate
-    Mat slot[4];
-    uint8_t *mb = b + L.off_mat;
-    for (int k = 0; k < 4; ++k) {
-        slot[k].hi = mb + (size_t)k * L.mat_bytes;
-        if (L.split) slot[k].lo = mb + (size_t)(4 + k) * L.mat_bytes;
-    }
+    const StagePlan &p = P.sp;
     const bool x0_split = p.split_final || (p.split_mask & 1u);
-    e = mirror_cast(X, ld, n, L.np, scal, 1, p.dtype, slot[0].hi, x0_split ? slot[0].lo : nullptr, L.np, s);
+    e = cast_x0(B, p.dtype, x0_split, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
 
     GemmArgs g{};
-    g.ld = L.np;
-    g.K = L.np;
-    g.scal = scal;
-    auto gemm = [&](Mat Lm, bool ls, Mat Rm, bool rs, const Mat *C0, bool c0s, float alpha, float beta, float gamma,
-                    Mat D, bool dsplit) -> hipError_t {
-        g.Lhi = Lm.hi; g.Llo = ls ? Lm.lo : nullptr;
-        g.Rhi = Rm.hi; g.Rlo = rs ? Rm.lo : nullptr;
-        g.C0hi = C0 ? C0->hi : nullptr; g.C0lo = (C0 && c0s) ? C0->lo : nullptr;
-        g.Dhi = D.hi; g.Dlo = dsplit ? D.lo : nullptr;
+    g.D = B.desc;
+    g.io_tab = B.io_tab;
+    g.io0 = B.io0;
+    // one product over every matrix, one launch per tile class
+    auto product = [&](int sl, bool ls, int sr, bool rs, int sc0, bool c0s, float alpha, float beta, float gamma,
+                       int sd, int epi) -> hipError_t {
+        g.sl = sl; g.sr = sr; g.sc0 = sc0; g.sd = sd; g.c0_split = c0s ? 1 : 0;
         g.alpha = alpha; g.beta = beta; g.gamma = gamma;
-        return gemm_sym_launch(g, p.dtype, dsplit ? EPI_STORE_SPLIT : EPI_STORE, s);
+        for (int c = 0; c < 2; ++c) {
+            if (!P.n_gemm[c]) continue;
+            g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
+            const hipError_t r = gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], P.n_gemm[c], s);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
     };
+    // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
     int cur = 0;
     bool cur_split = (p.split_mask & 1u) != 0;
     for (int t = 0; t < p.T; ++t) {
@@ -222,28 +316,102 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
         for (int k = 1; k < 4; ++k)
             if (k != cur) { if (pa < 0) pa = k; else if (pb < 0) pb = k; }
         const bool xs = sp && cur_split;  // X enters as a pair only in a split stage
+        const int st_epi = sp ? EPI_STORE_SPLIT : EPI_STORE;
         // A = X X
-        e = gemm(slot[cur], xs, slot[cur], xs, nullptr, false, 0.f, 1.f, 0.f, slot[pa], sp);
+        e = product(cur, xs, cur, xs, -1, false, 0.f, 1.f, 0.f, pa, st_epi);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         // B = b A + c A A
-        e = gemm(slot[pa], sp, slot[pa], sp, &slot[pa], sp, (float)p.b[t], (float)p.c[t], 0.f, slot[pb], sp);
+        e = product(pa, sp, pa, sp, pa, sp, (float)p.b[t], (float)p.c[t], 0.f, pb, st_epi);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         // X' = a X + X B
-        e = gemm(slot[cur], xs, slot[pb], sp, &slot[cur], cur_split, (float)p.a[t], 1.f, 0.f, slot[pa], next_split);
+        e = product(cur, xs, pb, sp, cur, cur_split, (float)p.a[t], 1.f, 0.f, pa,
+                    next_split ? EPI_STORE_SPLIT : EPI_STORE);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         cur = pa;
         cur_split = next_split;
     }
-    // 4. out = (X + lam X0 X_T) / 2
-    g.Lhi = slot[0].hi; g.Llo = p.split_final ? slot[0].lo : nullptr;
-    g.Rhi = slot[cur].hi; g.Rlo = p.split_final ? slot[cur].lo : nullptr;
-    g.C0hi = g.C0lo = nullptr;
-    g.Dhi = g.Dlo = nullptr;
-    g.out = out; g.ldo = ld; g.n = n; g.Xin = X; g.ldx = ld;
-    e = gemm_sym_launch(g, p.dtype, EPI_FINAL, s);
+    // out = (X + lam X0 X_T) / 2
+    e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, (const Scalars *)scal, info, p.T);
+    if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, B.desc, info, p.T);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
+}
+
+// Plan lookup/creation for (device, stream); builds tables when the shape or
+// the arena changed.
+int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hipStream_t s, Plan **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
+    StagePlan sp;
+    if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
+    Pool &pool = g_pool[{dev, s}];
+    if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns)) {
+        std::unique_ptr<Plan> P(new Plan());
+        P->mode = o.mode;
+        P->steps = steps;
+        P->sp = sp;
+        P->split_mask = sp.split_mask;
+        P->split_final = sp.split_final;
+        P->ns = ns;
+        layout_plan(*P);
+        if (pool.plan && hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
+        pool.plan = std::move(P);
+    }
+    Plan &P = *pool.plan;
+    void *base = nullptr;
+    const int st = get_workspace(pool, s, P.total, &base);
+    if (st != PSDPROJ_OK) return st;
+    if (P.base != base) {
+        const int bt = build_tables(P, base, s);
+        if (bt != PSDPROJ_OK) return bt;
+    }
+    *out = &P;
+    return PSDPROJ_OK;
+}
+
+}  // namespace
+
+int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
+                   psdproj_info *info, bool bound_only) {
+    StagePlan tmp;
+    if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
+    const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
+    if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
+    if (n < 0 || ld < (n > 1 ? n : 1)) return PSDPROJ_ERR_INVALID_ARG;
+    if (n == 0) return PSDPROJ_OK;
+    if (!X || (!out && !bound_only)) return PSDPROJ_ERR_INVALID_ARG;
+    if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *P = nullptr;
+    const int st = prepare(o, steps, std::vector<int64_t>{n}, s, &P);
+    if (st != PSDPROJ_OK) return st;
+    const IoArg io{X, out, ld};
+    return run_plan(*P, &io, o, s, info, bound_only);
+}
+
+int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_t *ld, const float *const *X,
+                float *const *out, hipStream_t s) {
+    StagePlan tmp;
+    if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
+    if (count < 0 || (count > 0 && (!n || !ld || !X || !out))) return PSDPROJ_ERR_INVALID_ARG;
+    std::vector<int64_t> ns;
+    std::vector<IoArg> ios;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 0 || ld[i] < (n[i] > 1 ? n[i] : 1) || (n[i] > 0 && (!X[i] || !out[i])))
+            return PSDPROJ_ERR_INVALID_ARG;
+        if (n[i] > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
+        if (n[i] == 0) continue;
+        ns.push_back(n[i]);
+        ios.push_back(IoArg{X[i], out[i], ld[i]});
+    }
+    if (ns.empty()) return PSDPROJ_OK;
+    const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
+    if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *P = nullptr;
+    const int st = prepare(o, steps, ns, s, &P);
+    if (st != PSDPROJ_OK) return st;
+    return run_plan(*P, ios.data(), o, s, nullptr, false);
 }
 
 psdproj_opts default_opts(int mode) {
@@ -256,9 +424,14 @@ psdproj_opts default_opts(int mode) {
 
 size_t workspace_bytes_for(int64_t n, int mode) {
     psdproj_opts o = default_opts(mode);
-    StagePlan p;
-    if (n <= 0 || !make_stage_plan(o, p)) return 0;
-    return make_layout(n, p, kDefaultLanczos).total;
+    StagePlan sp;
+    if (n <= 0 || !make_stage_plan(o, sp)) return 0;
+    Plan P;
+    P.sp = sp;
+    P.steps = kDefaultLanczos;
+    P.ns = {n};
+    layout_plan(P);
+    return P.total;
 }
 
 size_t pool_held(hipStream_t s) {
@@ -275,10 +448,9 @@ void pool_release(hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_pool.find({dev, s});
     if (it == g_pool.end()) return;
-    if (it->second.ptr) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(it->second.ptr);
-    }
+    (void)hipStreamSynchronize(s);
+    it->second.plan.reset();
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
     g_pool.erase(it);
 }
 
@@ -291,8 +463,8 @@ int gemm_count_for(const psdproj_opts &o) {
         const bool sp = (p.split_mask >> t) & 1u;
         const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         const bool xs = sp && cur_split;
-        g += xs ? 3 : 1;      // X X
-        g += sp ? 3 : 1;      // A A
+        g += xs ? 3 : 1;             // X X
+        g += sp ? 3 : 1;             // A A
         g += sp ? (xs ? 3 : 2) : 1;  // X B
         cur_split = next_split;
     }
@@ -327,16 +499,8 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
 
 int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld, const float *const *X, float *const *out,
                             int mode, psdproj_stream_t stream) {
-    if (count < 0 || (count > 0 && (!n || !ld || !X || !out))) return PSDPROJ_ERR_INVALID_ARG;
-    for (int i = 0; i < count; ++i)
-        if (n[i] < 0 || ld[i] < (n[i] > 1 ? n[i] : 1) || (n[i] > 0 && (!X[i] || !out[i])))
-            return PSDPROJ_ERR_INVALID_ARG;
     const psdproj_opts o = default_opts(mode);
-    for (int i = 0; i < count; ++i) {
-        const int st = run_projection(o, n[i], ld[i], X[i], out[i], (hipStream_t)stream, nullptr, false);
-        if (st != PSDPROJ_OK) return st;
-    }
-    return PSDPROJ_OK;
+    return run_batched(o, count, n, ld, X, out, (hipStream_t)stream);
 }
 
 size_t psdproj_workspace_bytes(int64_t n, int mode) { return workspace_bytes_for(n, mode); }
@@ -345,7 +509,6 @@ int psdproj_gemm_count(const psdproj_opts *opts, int mode) {
     psdproj_opts o = opts ? *opts : default_opts(mode);
     return gemm_count_for(o);
 }
-
 
 int psdproj_coefficients(int mode, double *abc, int cap) {
     psdproj_opts o = default_opts(mode);
@@ -362,8 +525,10 @@ int psdproj_coefficients(int mode, double *abc, int cap) {
 int psdproj_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (hipDeviceSynchronize() != hipSuccess) return PSDPROJ_ERR_HIP;
-    for (auto &kv : g_pool)
+    for (auto &kv : g_pool) {
+        kv.second.plan.reset();
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
     g_pool.clear();
     return PSDPROJ_OK;
 }
@@ -400,16 +565,46 @@ const char *psdproj_status_string(int status) {
     return "unknown status";
 }
 
+// Kernel-level product on caller buffers (tests and tooling): a one-matrix
+// descriptor whose slots are the given buffers. Synchronous.
 int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo, const void *R,
                      const void *Rlo, const void *C0, const void *C0lo, float alpha, float beta, float gamma, void *D,
                      void *Dlo, psdproj_stream_t stream) {
     if (dtype < 0 || dtype > 2 || n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D) return PSDPROJ_ERR_INVALID_ARG;
     if (dtype == DT_F32 && (Llo || Rlo || Dlo || C0lo)) return PSDPROJ_ERR_UNSUPPORTED;
-    GemmArgs g{};
-    g.Lhi = L; g.Llo = Llo; g.Rhi = R; g.Rlo = Rlo; g.C0hi = C0; g.C0lo = C0lo; g.Dhi = D; g.Dlo = Dlo;
-    g.ld = ld; g.K = n_p; g.alpha = alpha; g.beta = beta; g.gamma = gamma;
-    const hipError_t e = gemm_sym_launch(g, dtype, Dlo ? EPI_STORE_SPLIT : EPI_STORE, (hipStream_t)stream);
-    return e == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    MatDesc d;
+    memset(&d, 0, sizeof(d));
+    d.n = n_p;
+    d.np = n_p;
+    d.ldw = ld;
+    d.hi[0] = (void *)L; d.lo[0] = (void *)Llo;
+    d.hi[1] = (void *)R; d.lo[1] = (void *)Rlo;
+    d.hi[2] = (void *)C0; d.lo[2] = (void *)C0lo;
+    d.hi[3] = D; d.lo[3] = Dlo;
+    const int bm = gemm_pick_tile(n_p);
+    std::vector<WorkItem> tiles;
+    append_tile_order(tiles, 0, (int)(n_p / bm));
+    void *buf = nullptr;
+    const size_t bytes = align256(sizeof(MatDesc)) + sizeof(WorkItem) * tiles.size();
+    if (hipMalloc(&buf, bytes) != hipSuccess) return PSDPROJ_ERR_NO_MEMORY;
+    int status = PSDPROJ_OK;
+    WorkItem *wt = (WorkItem *)((uint8_t *)buf + align256(sizeof(MatDesc)));
+    if (hipMemcpy(buf, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(wt, tiles.data(), sizeof(WorkItem) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        status = PSDPROJ_ERR_HIP;
+    } else {
+        GemmArgs g{};
+        g.D = (const MatDesc *)buf;
+        g.tiles = wt;
+        g.sl = 0; g.sr = 1; g.sc0 = C0 ? 2 : -1; g.sd = 3; g.c0_split = C0lo ? 1 : 0;
+        g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+        const hipError_t e = gemm_sym_launch(g, dtype, Dlo ? EPI_STORE_SPLIT : EPI_STORE, Llo != nullptr,
+                                             Rlo != nullptr, bm, (int64_t)tiles.size(), s);
+        if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) status = PSDPROJ_ERR_HIP;
+    }
+    (void)hipFree(buf);
+    return status;
 }
 
 }  // extern "C"

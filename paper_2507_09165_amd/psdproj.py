@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsdproj.so")
 
-MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3}
+MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4}
 DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
@@ -276,10 +276,15 @@ class Server:
         _check(L.psdproj_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "psdproj_serve_create")
         self._h = h
 
-    def submit(self, n, X=None, out=None, target=1e-3, mode=-1, tag=0, ld=None):
-        """Returns a ticket, or raises PsdprojError (e.g. status 5 = rejected)."""
+    def submit(self, n=None, X=None, out=None, target=1e-3, mode=-1, tag=0, ld=None):
+        """Returns a ticket, or raises PsdprojError (e.g. status 5 = rejected).
+        With X given, n and ld come from it; out must match X."""
         if X is not None:
             n, ld = _check_matrix(X)
+            if out is None or _check_matrix(out, "out") != (n, ld):
+                raise ValueError("out must match X in shape and stride")
+        if n is None:
+            raise ValueError("n or X is required")
         req = Request(int(n), int(ld if ld is not None else max(1, n)),
                       None if X is None else X.data_ptr(), None if out is None else out.data_ptr(),
                       float(target), _mode(mode) if isinstance(mode, str) else int(mode), int(tag))

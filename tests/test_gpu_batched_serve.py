@@ -1,0 +1,86 @@
+"""Batched and served forms on the GPU.
+
+* Batched: one call covers every block (each launch spans all of them). Each
+  block's result must equal, bitwise, the single-matrix projection of that
+  block, and match the FP64 oracle evaluated with the device's bound.
+* Served: requests of mixed sizes and accuracy targets submitted to the
+  continuous-batching loop; each result must equal, bitwise, the same
+  request computed alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_09165_amd import inputs
+from paper_2507_09165_amd import psdproj as P
+from gpu_util import dev, rel_fro, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _single(X, mode):
+    out, info_t = P.project_ex(X, mode=mode)
+    return out, info_t
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp16", "fp32"])
+def test_batched_mixed_sizes_equal_single(mode):
+    import torch
+    sizes = [1, 32, 33, 100, 128, 257, 640, 1024, 1600]  # 1600 uses the 256 tile
+    say("batched", mode, sizes)
+    Xs = [to_dev(inputs.goe(n, 300 + n) if n > 1 else np.array([[0.7]], np.float32)) for n in sizes]
+    outs = P.project_batched(Xs, mode=mode)
+    singles = [P.project(X, mode=mode) for X in Xs]
+    torch.cuda.synchronize()
+    for n, a, b in zip(sizes, outs, singles):
+        assert torch.equal(a, b), n
+
+
+def test_batched_blocks_match_oracle():
+    import torch
+    sizes = inputs.batch_sizes(256, 7)[:24]
+    blocks = inputs.batch_blocks(sizes, 7)
+    say("batched C4 subset", list(sizes))
+    Xs = [to_dev(B) for B in blocks]
+    outs = P.project_batched(Xs, mode="bf16")
+    infos = []
+    for X in Xs:  # bound of each block (same kernels as inside the batch)
+        infos.append(P.spectral_bound(X))
+    torch.cuda.synchronize()
+    for B, o, info in zip(blocks, outs, infos):
+        ref, _ = oracle.project_poly(B.astype(np.float64), "bf16", lam=info["lambda"])
+        assert rel_fro(o.cpu().numpy(), ref) < 3e-2
+
+
+def test_batched_with_zero_sized_and_empty():
+    import torch
+    X = to_dev(inputs.goe(50, 1))
+    Z = torch.zeros(0, 0, device=dev())
+    outs = P.project_batched([X, Z, X], mode="fp16")
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[2])
+    assert P.project_batched([], mode="fp16") == []
+
+
+def test_served_results_equal_alone():
+    import torch
+    rng = np.random.default_rng(5)
+    sizes = [64, 300, 1000, 2100, 129, 777, 64, 1500]
+    targets = [1e-3, 1e-5, 1e-3, 1e-3, 1e-5, 1e-3, 1e-3, 1e-5]
+    Xs = [to_dev(inputs.goe(n, 500 + i)) for i, n in enumerate(sizes)]
+    modes = ["fp32" if t <= 1e-4 else "fp16_split" for t in targets]
+    alone = [P.project(X, mode=m) for X, m in zip(Xs, modes)]
+    torch.cuda.synchronize()
+    outs = [torch.full_like(X, float("nan")) for X in Xs]
+    say("serve", sizes)
+    with P.Server(slots=3) as s:
+        tks = []
+        for i in rng.permutation(len(sizes)):
+            tks.append((i, s.submit(X=Xs[i], out=outs[i], target=targets[i], tag=int(i))))
+        for i, tk in tks:
+            r = s.wait(tk, timeout_s=120)
+            assert r["status"] == 0 and r["tag"] == i
+        st = s.stats()
+    assert st["completed"] == len(sizes)
+    for i in range(len(sizes)):
+        assert torch.equal(outs[i], alone[i]), sizes[i]

@@ -18,7 +18,7 @@ from gpu_util import dev, rel_fro, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL_POLY = {"fp32": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "bf16": 3e-2}
+TOL_POLY = {"fp32": 1e-5, "fp32_emu": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "bf16": 3e-2}
 
 
 def _run(X32, mode, **opts):
@@ -54,7 +54,7 @@ def test_c1_fp32_n256():
     assert rel_fro(out, exact) < 2e-5
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp32"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp32", "fp32_emu"])
 @pytest.mark.parametrize("n", [200, 777])
 def test_goe_ragged(mode, n):
     X32 = inputs.goe(n, 2)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, nm), nm
 
 
-@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split"])
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu"])
 def test_library_coefficients_match_oracle(mode):
     lib_rows = P.coefficients(mode)
     ora_rows = oracle.stage_rows(mode)
@@ -44,6 +44,7 @@ def test_gemm_counts():
     assert P.gemm_count("fp16") == 22 == oracle.gemm_count("fp16")
     assert P.gemm_count("bf16") == 22
     assert P.gemm_count("fp32") == 31 == oracle.gemm_count("fp32")
+    assert P.gemm_count("fp32_emu") == 93  # 10 stages x 3 split products x 3 + 3
     # split products cost 2-3 GEMMs each: no split stages, split final only
     assert P.gemm_count("fp16_split", split_mask=0, split_final=1) >= 22
 

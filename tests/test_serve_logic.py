@@ -93,6 +93,10 @@ def test_cancel_pending_and_poll():
     with P.Server(slots=1, fake_executor=True, fake_tflops=1.0) as s:
         a = s.submit(n=2000)        # long
         b = s.submit(n=2000, tag=7)
+        t0 = time.time()
+        while s.stats()["running"] < 1:  # wait until the scheduler admitted `a`
+            assert time.time() - t0 < 10
+            time.sleep(0.001)
         assert s.poll(a) is None    # running
         assert s.cancel(b) == 0
         rb = s.wait(b, timeout_s=5)
