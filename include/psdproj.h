@@ -62,17 +62,25 @@ typedef enum {
     PSDPROJ_MODE_BF16 = 2,       /* Table 2 refined (T = 7), BF16 MFMA, 22 products   */
     PSDPROJ_MODE_FP16_SPLIT = 3, /* Table 2 refined, FP16 with hi+lo split operands in
                                     the stages of split_mask and the final product   */
-    PSDPROJ_MODE_FP32_EMU = 4    /* Table 1 refined (T = 10), every product on FP16
+    PSDPROJ_MODE_FP32_EMU = 4,   /* Table 1 refined (T = 10), every product on FP16
                                     hi+lo pairs (FP32-level operands at the FP16
                                     MFMA rate), 93 product-equivalents              */
+    PSDPROJ_MODE_FP8_FP16_SPLIT = 5 /* Table 2 refined, FP16 bulk; the split products
+                                    of split_mask (and the final product if
+                                    split_final) carry the correction as e4m3
+                                    codes: L_hi R_hi on FP16 MFMAs plus both
+                                    cross terms on one FP8 MFMA per 32 K, so a
+                                    split product costs 2 product-equivalents
+                                    instead of 3                                    */
 } psdproj_mode;
 
 typedef struct {
     int mode;                 /* psdproj_mode */
     int lanczos_steps;        /* 0 -> 20 (Section 3.4); at most 32 */
-    uint32_t split_mask;      /* FP16_SPLIT: bit t set -> stage t+1 uses split
-                                 products; 0 -> library default */
-    int split_final;          /* FP16_SPLIT: -1 default, 0 plain, 1 split final product */
+    uint32_t split_mask;      /* FP16_SPLIT, FP8_FP16_SPLIT: bit t set -> stage t+1
+                                 uses split products; 0 -> library default */
+    int split_final;          /* FP16_SPLIT, FP8_FP16_SPLIT: -1 default, 0 plain,
+                                 1 split final product */
     double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */
     int force_bound_fallback; /* test hook: halve the Lanczos bound so that the
                                  guard must replace it by ||X||_F */
@@ -119,9 +127,10 @@ int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld,
 /* Device bytes of workspace a projection of size n in `mode` uses. */
 size_t psdproj_workspace_bytes(int64_t n, int mode);
 
-/* Number of n_p x n_p products (GEMM equivalents) a projection runs:
- * 3 per stage + 1 for plain modes (22 half, 31 single); split products count
- * 2 or 3 each. opts may be NULL (then `mode` defaults apply). */
+/* Number of n_p x n_p products (FP16-product equivalents) a projection runs:
+ * 3 per stage + 1 for plain modes (22 half, 31 single); an FP16 split product
+ * counts 3 (2 if one operand is split), an FP8_FP16_SPLIT split product 2.
+ * opts may be NULL (then `mode` defaults apply). */
 int psdproj_gemm_count(const psdproj_opts *opts, int mode);
 
 /* Host copy of the run-time coefficients of `mode` (rescale folded in):
@@ -212,11 +221,30 @@ int psdproj_serve_destroy(psdproj_server *s);
  * symmetric work matrices (column-major, leading dimension ld >= n_p,
  * n_p a multiple of 128) in dtype 0 = FP32, 1 = FP16, 2 = BF16. Only the upper
  * tiles are computed and mirrored. *lo arguments may be NULL (unsplit);
- * Dlo != NULL requests a split output. */
+ * Dlo != NULL requests a split output. The product is queued on `stream` and
+ * the call returns at once (launch errors only). The library keeps the
+ * operand descriptor of the last call per device: a call whose pointers,
+ * sizes or tile schedule differ synchronises the device before replacing it,
+ * so repeated calls on the same buffers are bare kernel launches. */
 int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo,
                      const void *R, const void *Rlo, const void *C0, const void *C0lo,
                      float alpha, float beta, float gamma, void *D, void *Dlo,
                      psdproj_stream_t stream);
+
+/* psdproj_sym_gemm_pair8: the same product on FP16 matrices whose split parts
+ * are FP8 pairs (the PSDPROJ_MODE_FP8_FP16_SPLIT storage). For a split matrix
+ * M with FP16 part M_hi, the pair buffer (n_p x ld x 2 bytes, device) holds,
+ * per column j (2 ld bytes) and per group of 16 rows q, the 16 e4m3 codes of
+ * M_hi 2^e followed by the 16 codes of (M - M_hi) 2^(11+e), so that
+ * M = M_hi + 2^-(11+e) decode(lo codes). e_l, e_r, e_c0, e_d are the pair
+ * exponents of L, R, C0 and D (|e| <= 40). Lx and Rx are both given (pair
+ * product: L_hi R_hi + the two cross terms on FP8 MFMAs) or both NULL;
+ * C0x != NULL adds the pair correction of C0; Dx != NULL writes D's pair.
+ * Queued on `stream` like psdproj_sym_gemm. */
+int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *Lx,
+                           const void *R, const void *Rx, const void *C0, const void *C0x,
+                           float alpha, float beta, float gamma, void *D, void *Dx,
+                           int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream);
 
 #ifdef __cplusplus
 }

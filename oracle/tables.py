@@ -124,4 +124,5 @@ MODE_TABLE = {
     "bf16": "f_tilde_half",
     "fp16_split": "f_tilde_half",
     "fp32_emu": "f_tilde_single",
+    "fp8_fp16_split": "f_tilde_half",
 }

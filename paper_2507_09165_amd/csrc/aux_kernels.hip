@@ -69,9 +69,11 @@ __device__ __forceinline__ void tile_of(int t, int &I, int &J) {
 
 // Slot 0 of matrix m <- X / lam (64 x 64 tile pair (bi <= bj) of the padded
 // n_p x n_p matrix, transposed through LDS for the mirrored half).
-template <typename T, bool SPLIT>
+// X8: the split part is the FP8 pair of X0 (code exponent e8) instead of an
+// FP16 lo half.
+template <typename T, bool SPLIT, bool X8 = false>
 __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
-                                                   IoArg io0, float lo_scale) {
+                                                   IoArg io0, float lo_scale, int e8) {
     __shared__ float tile[64][65];
     const WorkItem wi = W[blockIdx.x];
     const MatDesc &d = D[wi.x];
@@ -82,6 +84,18 @@ __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkI
     const float s = (float)d.scal->inv_lam;
     T *Ohi = (T *)d.hi[0];
     T *Olo = (T *)d.lo[0];
+    uint8_t *Ox = (uint8_t *)d.lo[0];
+    const float hs = X8 ? __builtin_ldexpf(1.0f, e8) : 0.0f, ls = X8 ? __builtin_ldexpf(1.0f, 11 + e8) : 0.0f;
+    auto put = [&](int64_t i, int64_t j, float v) {
+        const T hi = cvt<T>(v);
+        Ohi[j * ldo + i] = hi;
+        if constexpr (SPLIT && X8) {
+            Ox[x8_index(i, j, ldo)] = e4m3((float)hi * hs);
+            Ox[x8_index(i, j, ldo) + 16] = e4m3((v - (float)hi) * ls);
+        } else if constexpr (SPLIT) {
+            Olo[j * ldo + i] = cvt<T>((v - (float)hi) * lo_scale);
+        }
+    };
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
     for (int c = ty; c < 64; c += 4) {
         const int64_t i = i0 + tx, j = j0 + c;
@@ -95,19 +109,9 @@ __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkI
             if (tx > c) tile[tx][c] = tile[c][tx];
         __syncthreads();
     }
-    for (int c = ty; c < 64; c += 4) {
-        const float v = tile[tx][c] * s;
-        const T hi = cvt<T>(v);
-        Ohi[(j0 + c) * ldo + i0 + tx] = hi;
-        if constexpr (SPLIT) Olo[(j0 + c) * ldo + i0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
-    }
+    for (int c = ty; c < 64; c += 4) put(i0 + tx, j0 + c, tile[tx][c] * s);
     if (bi == bj) return;
-    for (int c = ty; c < 64; c += 4) {
-        const float v = tile[c][tx] * s;
-        const T hi = cvt<T>(v);
-        Ohi[(i0 + c) * ldo + j0 + tx] = hi;
-        if constexpr (SPLIT) Olo[(i0 + c) * ldo + j0 + tx] = cvt<T>((v - (float)hi) * lo_scale);
-    }
+    for (int c = ty; c < 64; c += 4) put(j0 + tx, i0 + c, tile[c][tx] * s);
 }
 
 // ---------------------------------------------------------------------------
@@ -611,23 +615,31 @@ hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int fo
     return hipGetLastError();
 }
 
-hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, hipStream_t s) {
+hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, int e8, hipStream_t s) {
     if (B.count == 0 || B.n_cast == 0) return hipSuccess;
     const dim3 g((unsigned)B.n_cast), blk(256);
     switch (dtype) {
-        case 0: hipLaunchKernelGGL((cast_kernel<float, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+        case 0:
+            hipLaunchKernelGGL((cast_kernel<float, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
             break;
         case 1:
             if (split)
-                hipLaunchKernelGGL((cast_kernel<f16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 2048.0f);
+                hipLaunchKernelGGL((cast_kernel<f16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 2048.0f, 0);
             else
-                hipLaunchKernelGGL((cast_kernel<f16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+                hipLaunchKernelGGL((cast_kernel<f16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
             break;
         case 2:
             if (split)
-                hipLaunchKernelGGL((cast_kernel<bf16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+                hipLaunchKernelGGL((cast_kernel<bf16, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
             else
-                hipLaunchKernelGGL((cast_kernel<bf16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f);
+                hipLaunchKernelGGL((cast_kernel<bf16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
+            break;
+        case 3:  // FP16 with FP8 pairs
+            if (split)
+                hipLaunchKernelGGL((cast_kernel<f16, true, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 0.0f,
+                                   e8);
+            else
+                hipLaunchKernelGGL((cast_kernel<f16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
             break;
         default: return hipErrorInvalidValue;
     }

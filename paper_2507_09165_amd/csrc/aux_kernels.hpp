@@ -20,8 +20,9 @@ struct BatchLaunch {
 // Lanczos bound (Theorem 2) of every matrix into its Scalars.
 hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int force_fallback, double lam_override,
                           hipStream_t s);
-// Slot 0 <- X / lam in dtype (0 FP32, 1 FP16, 2 BF16), optionally hi + lo.
-hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, hipStream_t s);
+// Slot 0 <- X / lam in dtype (0 FP32, 1 FP16, 2 BF16, 3 FP16 with FP8 pairs
+// of code exponent e8), optionally split (hi + lo, or hi + FP8 pair).
+hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, int e8, hipStream_t s);
 
 size_t lanczos_work_doubles(int64_t n, int steps);
 int64_t symv_tile_count(int64_t n);

@@ -68,4 +68,36 @@ __device__ __forceinline__ IoArg io_of(const IoArg *tab, const IoArg &io0, int m
 
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// FP8 pair format of a split work matrix M = M_hi + 2^-11 M_lo (FP16 hi in
+// hi[slot]; the FP8 pair in lo[slot], which has the same byte size). Column j
+// of the pair buffer spans 2 ld bytes. Its rows are grouped by 16: group q
+// holds the 16 e4m3 codes of M_hi 2^e (rows 16q..16q+15), then the 16 codes
+// of (M - M_hi) 2^(11+e). So along K (the row index), every 32 bytes carry
+// 16 hi codes followed by the matching 16 lo codes. e is a per-slot power of
+// two chosen from a bound on |M| (entries of a symmetric matrix are bounded
+// by its spectral norm) so that both codes stay below the e4m3 maximum, 448.
+__device__ __forceinline__ int64_t x8_index(int64_t i, int64_t j, int64_t ld) {
+    return 2 * ld * j + 32 * (i >> 4) + (i & 15);
+}
+// Round to e4m3 (OCP, round to nearest even) after clamping to the finite
+// range; four values packed little-endian into one word.
+__device__ __forceinline__ float e4m3_clamp(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
+__device__ __forceinline__ uint32_t e4m3x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), w, true);
+    return (uint32_t)w;
+}
+__device__ __forceinline__ uint8_t e4m3(float a) {
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), 0.0f, 0, false) & 0xFF);
+}
+// Byte q (compile-time after unrolling) of a packed word, decoded.
+__device__ __forceinline__ float e4m3_byte(uint32_t w, int q) {
+    switch (q) {
+        case 0: return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
+        case 1: return __builtin_amdgcn_cvt_f32_fp8((int)w, 1);
+        case 2: return __builtin_amdgcn_cvt_f32_fp8((int)w, 2);
+        default: return __builtin_amdgcn_cvt_f32_fp8((int)w, 3);
+    }
+}
+
 }  // namespace psd

@@ -57,6 +57,18 @@ __device__ __forceinline__ void mma(f32x16 &acc, u32x4 a, u32x4 b, bf16) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
 }
 
+// FP8 cross terms of a pair product on the scaled e4m3 MFMA (64 K slots per
+// lane pair). a = [hi codes | lo codes] of L, b = [lo codes | hi codes] of R
+// over the same 16 K values per lane half, so slot p pairs L_hi with R_lo in
+// the first half and L_lo with R_hi in the second. The E8M0 block scales
+// (uniform: every byte of sa / sb) undo the pair exponents and the 2^11.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void mma_x8(f32x16 &acc, u32x4 a0, u32x4 a1, u32x4 b0, u32x4 b1, int sa, int sb) {
+    const i32x8 a = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+    const i32x8 b = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
+}
+
 __device__ __forceinline__ u32x4 scale_frag(u32x4 v, f16) {
     f16x8 h = __builtin_bit_cast(f16x8, v);
     h = h * (f16)2048.0f;
@@ -101,10 +113,16 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST>
+// X8: split parts are FP8 pairs (FP16 hi + e4m3 hi/lo codes) instead of FP16
+// hi + FP16 lo; the pair product is L_hi R_hi on FP16 MFMAs plus both cross
+// terms on one FP8 MFMA per 32 K. Requires T = f16 and LS == RS.
+template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
+    static_assert(!X8 || (sizeof(T) == 2 && LS == RS), "FP8 pairs: FP16 hi, both operands split");
+    static_assert(!(X8 && LS) || ROWB >= 64, "FP8 pair units are 64 bytes of a row");
+    constexpr bool PAIR8 = X8 && LS;          // FP8 cross terms in the main loop
     constexpr int NCH = ROWB / 16;            // 16-byte chunks per LDS row
-    constexpr int NSUB = NCH / 2;             // MFMA K-substeps per row
+    constexpr int NSUB = PAIR8 ? NCH / 4 : NCH / 2;  // K-units per row: 16 K (32 K with FP8 pairs)
     constexpr int NLP = LS ? 2 : 1;
     constexpr int NRP = RS ? 2 : 1;
     constexpr int PANEL = BM * ROWB;
@@ -185,9 +203,30 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     }
 
     const int64_t nk = dm.np / BK;
-    // Fragments of one K-substep: operand panel p, MFMA block m.
-    typedef u32x4 Frag[NLP + NRP][MI];
+    // Fragments of one K-unit, [part][MFMA block m]. Plain and FP16 pairs:
+    // one part per operand panel. FP8 pairs: L_hi (two 16-K substeps),
+    // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo).
+    constexpr int NFP = PAIR8 ? 8 : NLP + NRP;
+    typedef u32x4 Frag[NFP][MI];
+    // E8M0 scale codes 2^(c - 127), replicated into every byte
+    const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
+    const int sb8 = PAIR8 ? (int)((uint32_t)(127 - g.es_r) * 0x01010101u) : 0;
     auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
+        if constexpr (PAIR8) {
+            const int hg = lane >> 5;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int m = 0; m < MI; ++m) {
+                    const int cl = 4 * sub + 2 * h + hg;  // FP16: substep h, lane half hg
+                    const int cx = 4 * sub + 2 * hg + h;  // codes: 16 K of lane half hg, hi (h = 0) / lo
+                    f[h][m] = *(const u32x4 *)(base + roff_a[m] + ((cl ^ key_a[m]) << 4));
+                    f[2 + h][m] = *(const u32x4 *)(base + PANEL + roff_a[m] + ((cx ^ key_a[m]) << 4));
+                    f[4 + h][m] = *(const u32x4 *)(base + 2 * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
+                    f[6 + h][m] = *(const u32x4 *)(base + 3 * PANEL + roff_b[m] + ((cx ^ key_b[m]) << 4));
+                }
+            return;
+        }
         const int cl = 2 * sub + (lane >> 5);
 #pragma unroll
         for (int p = 0; p < NLP; ++p)
@@ -205,7 +244,11 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int ni = 0; ni < MI; ++ni) {
-                if constexpr (LS || RS) {
+                if constexpr (PAIR8) {
+                    mma(acc[mi][ni], f[0][mi], f[4][ni], T{});
+                    mma(acc[mi][ni], f[1][mi], f[5][ni], T{});
+                    mma_x8(acc[mi][ni], f[2][mi], f[3][mi], f[7][ni], f[6][ni], sa8, sb8);
+                } else if constexpr (LS || RS) {
                     mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
                     if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
                     if constexpr (LS) mma(acc[mi][ni], f[1][mi], f[NLP][ni], T{});
@@ -214,8 +257,6 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 }
             }
     };
-    constexpr int NMF = MI * MI * (1 + (LS ? 1 : 0) + (RS ? 1 : 0));  // MFMAs per substep
-    constexpr int NDS = (NLP + NRP) * MI;                            // ds_reads per substep
     Frag fr[2];
     // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
     // Every wave issues exactly NLD loads per iteration (the index is clamped
@@ -255,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     // ---------------- epilogue ----------------
     // Accumulator layout of a 32x32 MFMA block: lane l, register e holds
     // row 8 (e / 4) + 4 (l / 32) + (e % 4), column l % 32.
-    const float acc_scale = (LS || RS) ? 1.0f / Elt<T>::kSplit : 1.0f;
+    const float acc_scale = ((LS || RS) && !X8) ? 1.0f / Elt<T>::kSplit : 1.0f;
     const bool diag = (bi == bj);
     if constexpr (EPI == EPI_FINAL) {
         if (dm.scal->nonfinite) return;  // leave the output untouched
@@ -288,6 +329,11 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const T *C0hi = g.sc0 >= 0 ? (const T *)dm.hi[g.sc0] : nullptr;
         const T *C0lo = (g.sc0 >= 0 && g.c0_split) ? (const T *)dm.lo[g.sc0] : nullptr;
         const float c0lo = 1.0f / Elt<T>::kSplit;
+        // FP8 pairs: code scales of the addend and of the output slot
+        const float c0x = X8 ? __builtin_ldexpf(1.0f, -(11 + g.es_c0)) : 0.0f;
+        const float dhs = X8 ? __builtin_ldexpf(1.0f, g.es_d) : 0.0f;
+        const float dls = X8 ? __builtin_ldexpf(1.0f, 11 + g.es_d) : 0.0f;
+        uint8_t *Dx = (uint8_t *)dm.lo[g.sd];
         typedef T t4 __attribute__((ext_vector_type(4)));
 #pragma clang loop unroll(full)
         for (int mi = 0; mi < MI; ++mi)
@@ -305,25 +351,48 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma clang loop unroll(full)
                         for (int q = 0; q < 4; ++q) v[q] += g.alpha * to_f(c[q]);
                         if (C0lo) {
-                            const t4 cl = *(const t4 *)(C0lo + j * ld + ib);
+                            if constexpr (X8) {
+                                const uint32_t w =
+                                    *(const uint32_t *)((const uint8_t *)C0lo + x8_index(ib, j, ld) + 16);
 #pragma clang loop unroll(full)
-                            for (int q = 0; q < 4; ++q) v[q] += g.alpha * (to_f(cl[q]) * c0lo);
+                                for (int q = 0; q < 4; ++q) v[q] += g.alpha * (e4m3_byte(w, q) * c0x);
+                            } else {
+                                const t4 cl = *(const t4 *)(C0lo + j * ld + ib);
+#pragma clang loop unroll(full)
+                                for (int q = 0; q < 4; ++q) v[q] += g.alpha * (to_f(cl[q]) * c0lo);
+                            }
                         }
                     }
+                    constexpr bool SPL16 = EPI == EPI_STORE_SPLIT && !X8;
+                    constexpr bool SPL8 = EPI == EPI_STORE_SPLIT && X8;
                     t4 hi, lo;
 #pragma clang loop unroll(full)
                     for (int q = 0; q < 4; ++q) {
                         if (ib + q == j) v[q] += g.gamma;
                         hi[q] = from_f<T>(v[q]);
-                        lo[q] = from_f<T>((v[q] - to_f(hi[q])) * Elt<T>::kSplit);
+                        if constexpr (SPL16) lo[q] = from_f<T>((v[q] - to_f(hi[q])) * Elt<T>::kSplit);
+                    }
+                    uint32_t h8 = 0, l8 = 0;
+                    if constexpr (SPL8) {
+                        h8 = e4m3x4(to_f(hi[0]) * dhs, to_f(hi[1]) * dhs, to_f(hi[2]) * dhs, to_f(hi[3]) * dhs);
+                        l8 = e4m3x4((v[0] - to_f(hi[0])) * dls, (v[1] - to_f(hi[1])) * dls,
+                                    (v[2] - to_f(hi[2])) * dls, (v[3] - to_f(hi[3])) * dls);
                     }
                     if (!diag) {
                         *(t4 *)(Dhi + j * ld + ib) = hi;
-                        if constexpr (EPI == EPI_STORE_SPLIT) *(t4 *)(Dlo + j * ld + ib) = lo;
+                        if constexpr (SPL16) *(t4 *)(Dlo + j * ld + ib) = lo;
+                        if constexpr (SPL8) {
+                            *(uint32_t *)(Dx + x8_index(ib, j, ld)) = h8;
+                            *(uint32_t *)(Dx + x8_index(ib, j, ld) + 16) = l8;
+                        }
 #pragma clang loop unroll(full)
                         for (int q = 0; q < 4; ++q) {
                             Dhi[(ib + q) * ld + j] = hi[q];
-                            if constexpr (EPI == EPI_STORE_SPLIT) Dlo[(ib + q) * ld + j] = lo[q];
+                            if constexpr (SPL16) Dlo[(ib + q) * ld + j] = lo[q];
+                            if constexpr (SPL8) {
+                                Dx[x8_index(j, ib + q, ld)] = (uint8_t)(h8 >> (8 * q));
+                                Dx[x8_index(j, ib + q, ld) + 16] = (uint8_t)(l8 >> (8 * q));
+                            }
                         }
                     } else {
 #pragma clang loop unroll(full)
@@ -332,9 +401,16 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                             if (i > j) continue;
                             Dhi[j * ld + i] = hi[q];
                             Dhi[i * ld + j] = hi[q];
-                            if constexpr (EPI == EPI_STORE_SPLIT) {
+                            if constexpr (SPL16) {
                                 Dlo[j * ld + i] = lo[q];
                                 Dlo[i * ld + j] = lo[q];
+                            }
+                            if constexpr (SPL8) {
+                                const uint8_t hb = (uint8_t)(h8 >> (8 * q)), lb = (uint8_t)(l8 >> (8 * q));
+                                Dx[x8_index(i, j, ld)] = hb;
+                                Dx[x8_index(i, j, ld) + 16] = lb;
+                                Dx[x8_index(j, i, ld)] = hb;
+                                Dx[x8_index(j, i, ld) + 16] = lb;
                             }
                         }
                     }
@@ -369,14 +445,15 @@ void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T) {
 // The 128 tile (two workgroups per CU) measured faster than the 256 tile at
 // n = 10^4 (37.1 vs 38.0 ms for a plain FP16 projection), so it is the default;
 // the 256 tile remains available through the tuning hook.
-int gemm_pick_tile(int64_t K) {
+int gemm_pick_tile(int64_t K, int dtype) {
+    if (dtype == DT_F16X8) return 128;  // FP8-pair kernels exist for the 128 tile only
     const int o = g_tile_override;
     if (o && K % o == 0) return o;
     return 128;
 }
 
 // Padded order of the work matrices: a multiple of the tile the launcher will
-// pick for it (the override, else 256 from n = 1536 on, else 128). Any choice
+// pick for it (the override, else 128). Any choice
 // gives bitwise-identical results: every element accumulates its K products
 // in the same order whatever the tile shape, and padding only adds zeros.
 int64_t gemm_padded_size(int64_t n) {
@@ -386,24 +463,35 @@ int64_t gemm_padded_size(int64_t n) {
     return round_up(m, kTile);
 }
 
-// LDS configuration per (tile, operand panels): the 128 tile keeps two
-// 128-byte stages (64 KB, two workgroups per CU); the 256 tile uses a 4-stage
-// ring within 128 KB with rows as wide as that allows.
+// LDS configuration per (tile, operand panels). The 128 tile keeps two
+// stages within 80 KB, so two workgroups share a CU (160 KB of LDS) whether or
+// not the operands are split: plain panels get 128-byte rows, split panels
+// 64-byte rows (measured 1.7% faster per split projection than one 128-KB
+// workgroup per CU). The 256 tile uses 128 KB: a 4-stage ring for plain
+// operands, two stages of 64-byte rows for split ones.
 template <int BM, int NP> struct LdsCfg {
-    static constexpr int NST = BM == 256 ? 4 : 2;
-    static constexpr int ROWB_MAX = (128 * 1024) / (NST * NP * BM);
+    static constexpr int NST = (BM == 256 && NP == 2) ? 4 : 2;
+    static constexpr int BUDGET = BM == 256 ? 128 * 1024 : 80 * 1024;
+    static constexpr int ROWB_MAX = BUDGET / (NST * NP * BM);
     static constexpr int ROWB = ROWB_MAX >= 128 ? 128 : ROWB_MAX >= 64 ? 64 : 32;
 };
 
-template <typename T, bool LS, bool RS, int EPI, int BM>
+template <typename T, bool LS, bool RS, int EPI, int BM, bool X8 = false>
 static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s) {
     constexpr int NP = 2 + (LS ? 1 : 0) + (RS ? 1 : 0);
     constexpr int ROWB = LdsCfg<BM, NP>::ROWB;
     constexpr int NST = LdsCfg<BM, NP>::NST;
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST>), dim3((unsigned)ntiles), dim3(kThreads), 0, s,
-                       g);
+    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST, X8>), dim3((unsigned)ntiles), dim3(kThreads), 0,
+                       s, g);
     return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s) {
+    if (bm != 128) return hipErrorInvalidValue;
+    return pair ? launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s)
+                : launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s);
 }
 
 template <typename T, bool LS, bool RS, int EPI>
@@ -441,6 +529,14 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool 
             return epi == EPI_STORE ? launch_t<float, false, false, EPI_STORE>(g, bm, ntiles, s)
                                     : launch_t<float, false, false, EPI_FINAL>(g, bm, ntiles, s);
         case DT_F16: return launch_epi<f16>(g, epi, ls, rs, bm, ntiles, s);
+        case DT_F16X8:
+            if (ls != rs) return hipErrorInvalidValue;
+            switch (epi) {
+                case EPI_STORE: return launch_x8<EPI_STORE>(g, ls, bm, ntiles, s);
+                case EPI_STORE_SPLIT: return launch_x8<EPI_STORE_SPLIT>(g, ls, bm, ntiles, s);
+                case EPI_FINAL: return launch_x8<EPI_FINAL>(g, ls, bm, ntiles, s);
+            }
+            return hipErrorInvalidValue;
         case DT_BF16: return launch_epi<bf16>(g, epi, ls, rs, bm, ntiles, s);
     }
     return hipErrorInvalidValue;

@@ -6,7 +6,9 @@
 
 namespace psd {
 
-enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+// DT_F16X8: FP16 work matrices whose split slots carry FP8 pairs (see
+// x8_index) instead of FP16 lo halves.
+enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F16X8 = 3 };
 enum Epi { EPI_STORE = 0, EPI_STORE_SPLIT = 1, EPI_FINAL = 2 };
 
 // Output tile edge; work matrices are zero-padded to a multiple of it.
@@ -24,6 +26,7 @@ struct GemmArgs {
     int sl, sr, sc0, sd;
     int c0_split;
     float alpha, beta, gamma;
+    int es_l, es_r, es_c0, es_d;  // FP8-pair code exponents of the slots (DT_F16X8)
 };
 
 // ls / rs: L / R carry lo halves. bm: tile edge (128 or 256; it must divide
@@ -33,9 +36,9 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool 
 // Append matrix m's upper tiles (T x T tile grid) in the blocked schedule order.
 void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T);
 
-// Tile edge the launcher uses for a padded size K, and the padded size used for
-// a logical size n (a multiple of the tile it will run with).
-int gemm_pick_tile(int64_t K);
+// Tile edge the launcher uses for a padded size K and dtype, and the padded
+// size used for a logical size n (a multiple of the tile it will run with).
+int gemm_pick_tile(int64_t K, int dtype);
 int64_t gemm_padded_size(int64_t n);
 // Tuning hook: force the tile edge (0 restores the automatic choice).
 void gemm_set_tile_override(int bm);

@@ -41,7 +41,44 @@ struct StagePlan {
     int dtype = DT_F32;
     uint32_t split_mask = 0;
     bool split_final = false;
+    // FP8-pair code exponents (DT_F16X8): X_t (t = 0..T), A and B of stage t
+    int ex[17], ea[16], eb[16];
 };
+
+// Exponent e of an FP8 pair for a matrix whose entries are bounded by `bound`:
+// codes |M_hi| 2^e and |M - M_hi| 2^(11+e) <= |M| 2^e stay at or below 256,
+// leaving a factor 1.75 to the e4m3 maximum for rounding and a bound that is
+// slightly loose.
+int pair_exponent(double bound) {
+    const int e = (int)floor(log2(256.0 / fmax(bound, 1e-30)));
+    return e < -40 ? -40 : (e > 40 ? 40 : e);
+}
+
+// Bounds on the stage matrices. X0 = X / lam has spectral norm <= 1 when lam
+// bounds ||X||_2 (2% slack covers a Lanczos bound a little below it). Stage t
+// maps eigenvalues x of X_t to a x + b x^3 + c x^5 with A = X_t^2 <= bx^2 and
+// B = b A + c A^2; entries of a symmetric matrix are bounded by its spectral
+// norm. Maxima are taken on a fine grid.
+void pair_exponents(StagePlan &p) {
+    const int G = 4096;
+    double bx = 1.02;
+    p.ex[0] = pair_exponent(bx);
+    for (int t = 0; t < p.T; ++t) {
+        const double ba = bx * bx;
+        double bb = 0.0, bn = 0.0;
+        for (int k = 0; k <= G; ++k) {
+            const double y = ba * k / G;  // eigenvalue of A
+            bb = fmax(bb, fabs(p.b[t] * y + p.c[t] * y * y));
+            const double x = bx * k / G;  // eigenvalue of X_t
+            const double x2 = x * x;
+            bn = fmax(bn, fabs(x * (p.a[t] + x2 * (p.b[t] + p.c[t] * x2))));
+        }
+        p.ea[t] = pair_exponent(ba);
+        p.eb[t] = pair_exponent(bb);
+        bx = bn;
+        p.ex[t + 1] = pair_exponent(bx);
+    }
+}
 
 bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
     const StageCoef *tab;
@@ -57,6 +94,8 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
             tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_BF16; break;
         case PSDPROJ_MODE_FP32_EMU:
             tab = kTildeSingle; T = 10; nres = kSingleRescaled; res = kSingleRescale; p.dtype = DT_F16; break;
+        case PSDPROJ_MODE_FP8_FP16_SPLIT:
+            tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_F16X8; break;
         default: return false;
     }
     p.T = T;
@@ -66,7 +105,7 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
         p.b[t] = tab[t].b * s;
         p.c[t] = tab[t].c * s;
     }
-    if (o.mode == PSDPROJ_MODE_FP16_SPLIT) {
+    if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT) {
         p.split_mask = (o.split_mask ? o.split_mask : kDefaultSplitMask) & ((1u << T) - 1);
         p.split_final = o.split_final < 0 ? kDefaultSplitFinal : o.split_final != 0;
     } else if (o.mode == PSDPROJ_MODE_FP32_EMU) {
@@ -74,6 +113,7 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
         p.split_mask = (1u << T) - 1;
         p.split_final = true;
     }
+    pair_exponents(p);
     return true;
 }
 
@@ -143,7 +183,7 @@ void layout_plan(Plan &P) {
         P.n_vec += vec_block_count(n);
         P.n_symv += symv_tile_count(n);
         P.n_cast += cast_tile_count(L.np);
-        const int bm = gemm_pick_tile(L.np);
+        const int bm = gemm_pick_tile(L.np, P.sp.dtype);
         const int64_t T = L.np / bm;
         P.n_gemm[bm == 256 ? 0 : 1] += T * (T + 1) / 2;
     }
@@ -186,7 +226,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < cast_tile_count(L.np); ++i) wc.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
-        const int bm = gemm_pick_tile(L.np);
+        const int bm = gemm_pick_tile(L.np, P.sp.dtype);
         append_tile_order(wg[bm == 256 ? 0 : 1], (uint32_t)m, (int)(L.np / bm));
     }
     if (hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
@@ -289,7 +329,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
     }
     const StagePlan &p = P.sp;
     const bool x0_split = p.split_final || (p.split_mask & 1u);
-    e = cast_x0(B, p.dtype, x0_split, s);
+    e = cast_x0(B, p.dtype, x0_split, p.ex[0], s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
 
     GemmArgs g{};
@@ -297,16 +337,20 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
     g.io_tab = B.io_tab;
     g.io0 = B.io0;
     // one product over every matrix, one launch per tile class
+    // FP8-pair exponent of the matrix each slot currently holds
+    int slot_e[4] = {p.ex[0], 0, 0, 0};
     auto product = [&](int sl, bool ls, int sr, bool rs, int sc0, bool c0s, float alpha, float beta, float gamma,
-                       int sd, int epi) -> hipError_t {
+                       int sd, int epi, int e_out) -> hipError_t {
         g.sl = sl; g.sr = sr; g.sc0 = sc0; g.sd = sd; g.c0_split = c0s ? 1 : 0;
         g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+        g.es_l = slot_e[sl]; g.es_r = slot_e[sr]; g.es_c0 = sc0 >= 0 ? slot_e[sc0] : 0; g.es_d = e_out;
         for (int c = 0; c < 2; ++c) {
             if (!P.n_gemm[c]) continue;
             g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
             const hipError_t r = gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], P.n_gemm[c], s);
             if (r != hipSuccess) return r;
         }
+        if (epi != EPI_FINAL) slot_e[sd] = e_out;
         return hipSuccess;
     };
     // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
@@ -321,20 +365,20 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         const bool xs = sp && cur_split;  // X enters as a pair only in a split stage
         const int st_epi = sp ? EPI_STORE_SPLIT : EPI_STORE;
         // A = X X
-        e = product(cur, xs, cur, xs, -1, false, 0.f, 1.f, 0.f, pa, st_epi);
+        e = product(cur, xs, cur, xs, -1, false, 0.f, 1.f, 0.f, pa, st_epi, p.ea[t]);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         // B = b A + c A A
-        e = product(pa, sp, pa, sp, pa, sp, (float)p.b[t], (float)p.c[t], 0.f, pb, st_epi);
+        e = product(pa, sp, pa, sp, pa, sp, (float)p.b[t], (float)p.c[t], 0.f, pb, st_epi, p.eb[t]);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         // X' = a X + X B
         e = product(cur, xs, pb, sp, cur, cur_split, (float)p.a[t], 1.f, 0.f, pa,
-                    next_split ? EPI_STORE_SPLIT : EPI_STORE);
+                    next_split ? EPI_STORE_SPLIT : EPI_STORE, p.ex[t + 1]);
         if (e != hipSuccess) return PSDPROJ_ERR_HIP;
         cur = pa;
         cur_split = next_split;
     }
     // out = (X + lam X0 X_T) / 2
-    e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL);
+    e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL, 0);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, B.desc, info, p.T);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
@@ -460,24 +504,39 @@ void pool_release(hipStream_t s) {
 int gemm_count_for(const psdproj_opts &o) {
     StagePlan p;
     if (!make_stage_plan(o, p)) return -1;
+    // an FP16 pair product is 3 FP16 products; an FP8 pair product is one FP16
+    // product plus one FP8 product of twice the K at twice the rate
+    const int pair = p.dtype == DT_F16X8 ? 2 : 3;
     int g = 0;
     bool cur_split = (p.split_mask & 1u) != 0;
     for (int t = 0; t < p.T; ++t) {
         const bool sp = (p.split_mask >> t) & 1u;
         const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         const bool xs = sp && cur_split;
-        g += xs ? 3 : 1;             // X X
-        g += sp ? 3 : 1;             // A A
-        g += sp ? (xs ? 3 : 2) : 1;  // X B
+        g += xs ? pair : 1;             // X X
+        g += sp ? pair : 1;             // A A
+        g += sp ? (xs ? pair : 2) : 1;  // X B
         cur_split = next_split;
     }
-    g += p.split_final ? 3 : 1;
+    g += p.split_final ? pair : 1;
     return g;
 }
 
 }  // namespace psd
 
 using namespace psd;
+
+// psdproj_sym_gemm keeps the descriptor and tile list of its last call per
+// device, so repeated calls with the same operands are bare kernel launches.
+struct SymGemmCache {
+    MatDesc d{};
+    int bm = 0;
+    std::vector<WorkItem> tiles;
+    void *buf = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_sg_mu;
+static std::map<int, SymGemmCache> g_sg;
 
 extern "C" {
 
@@ -533,6 +592,10 @@ int psdproj_release(void) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     }
     g_pool.clear();
+    std::lock_guard<std::mutex> lk2(g_sg_mu);
+    for (auto &kv : g_sg)
+        if (kv.second.buf) (void)hipFree(kv.second.buf);
+    g_sg.clear();
     return PSDPROJ_OK;
 }
 
@@ -569,13 +632,12 @@ const char *psdproj_status_string(int status) {
 }
 
 // Kernel-level product on caller buffers (tests and tooling): a one-matrix
-// descriptor whose slots are the given buffers. Synchronous.
-int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo, const void *R,
-                     const void *Rlo, const void *C0, const void *C0lo, float alpha, float beta, float gamma, void *D,
-                     void *Dlo, psdproj_stream_t stream) {
-    if (dtype < 0 || dtype > 2 || n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D) return PSDPROJ_ERR_INVALID_ARG;
-    if (dtype == DT_F32 && (Llo || Rlo || Dlo || C0lo)) return PSDPROJ_ERR_UNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
+// descriptor whose slots are the given buffers; queued on the stream.
+static int sym_gemm_impl(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo, const void *R,
+                         const void *Rlo, const void *C0, const void *C0lo, float alpha, float beta, float gamma,
+                         void *D, void *Dlo, const int *es, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     MatDesc d;
     memset(&d, 0, sizeof(d));
     d.n = n_p;
@@ -585,29 +647,66 @@ int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const vo
     d.hi[1] = (void *)R; d.lo[1] = (void *)Rlo;
     d.hi[2] = (void *)C0; d.lo[2] = (void *)C0lo;
     d.hi[3] = D; d.lo[3] = Dlo;
-    const int bm = gemm_pick_tile(n_p);
+    const int bm = gemm_pick_tile(n_p, dtype);
     std::vector<WorkItem> tiles;
     append_tile_order(tiles, 0, (int)(n_p / bm));
-    void *buf = nullptr;
-    const size_t bytes = align256(sizeof(MatDesc)) + sizeof(WorkItem) * tiles.size();
-    if (hipMalloc(&buf, bytes) != hipSuccess) return PSDPROJ_ERR_NO_MEMORY;
-    int status = PSDPROJ_OK;
-    WorkItem *wt = (WorkItem *)((uint8_t *)buf + align256(sizeof(MatDesc)));
-    if (hipMemcpy(buf, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(wt, tiles.data(), sizeof(WorkItem) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        status = PSDPROJ_ERR_HIP;
-    } else {
-        GemmArgs g{};
-        g.D = (const MatDesc *)buf;
-        g.tiles = wt;
-        g.sl = 0; g.sr = 1; g.sc0 = C0 ? 2 : -1; g.sd = 3; g.c0_split = C0lo ? 1 : 0;
-        g.alpha = alpha; g.beta = beta; g.gamma = gamma;
-        const hipError_t e = gemm_sym_launch(g, dtype, Dlo ? EPI_STORE_SPLIT : EPI_STORE, Llo != nullptr,
-                                             Rlo != nullptr, bm, (int64_t)tiles.size(), s);
-        if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) status = PSDPROJ_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_sg_mu);
+    SymGemmCache &c = g_sg[dev];
+    const bool same = c.buf && c.bm == bm && c.tiles.size() == tiles.size() && !memcmp(&c.d, &d, sizeof(d)) &&
+                      !memcmp(c.tiles.data(), tiles.data(), sizeof(WorkItem) * tiles.size());
+    if (!same) {
+        // The cached copy may still be read by a launch in flight.
+        if (hipDeviceSynchronize() != hipSuccess) return PSDPROJ_ERR_HIP;
+        const size_t bytes = align256(sizeof(MatDesc)) + sizeof(WorkItem) * tiles.size();
+        if (bytes > c.bytes) {
+            if (c.buf) (void)hipFree(c.buf);
+            c.buf = nullptr;
+            c.bytes = 0;
+            if (hipMalloc(&c.buf, bytes) != hipSuccess) {
+                c.buf = nullptr;
+                return PSDPROJ_ERR_NO_MEMORY;
+            }
+            c.bytes = bytes;
+        }
+        c.tiles.clear();  // invalid until both uploads succeed
+        WorkItem *wt = (WorkItem *)((uint8_t *)c.buf + align256(sizeof(MatDesc)));
+        if (hipMemcpy(c.buf, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(wt, tiles.data(), sizeof(WorkItem) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return PSDPROJ_ERR_HIP;
+        c.d = d;
+        c.bm = bm;
+        c.tiles = tiles;
     }
-    (void)hipFree(buf);
-    return status;
+    GemmArgs g{};
+    g.D = (const MatDesc *)c.buf;
+    g.tiles = (const WorkItem *)((uint8_t *)c.buf + align256(sizeof(MatDesc)));
+    g.sl = 0; g.sr = 1; g.sc0 = C0 ? 2 : -1; g.sd = 3; g.c0_split = C0lo ? 1 : 0;
+    g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+    if (es) { g.es_l = es[0]; g.es_r = es[1]; g.es_c0 = es[2]; g.es_d = es[3]; }
+    const hipError_t e = gemm_sym_launch(g, dtype, Dlo ? EPI_STORE_SPLIT : EPI_STORE, Llo != nullptr, Rlo != nullptr,
+                                         bm, (int64_t)tiles.size(), s);
+    return e == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
+}
+
+int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const void *Llo, const void *R,
+                     const void *Rlo, const void *C0, const void *C0lo, float alpha, float beta, float gamma, void *D,
+                     void *Dlo, psdproj_stream_t stream) {
+    if (dtype < 0 || dtype > 2 || n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D) return PSDPROJ_ERR_INVALID_ARG;
+    if (dtype == DT_F32 && (Llo || Rlo || Dlo || C0lo)) return PSDPROJ_ERR_UNSUPPORTED;
+    return sym_gemm_impl(dtype, n_p, ld, L, Llo, R, Rlo, C0, C0lo, alpha, beta, gamma, D, Dlo, nullptr,
+                         (hipStream_t)stream);
+}
+
+int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *Lx, const void *R, const void *Rx,
+                           const void *C0, const void *C0x, float alpha, float beta, float gamma, void *D, void *Dx,
+                           int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream) {
+    if (n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D || (C0x && !C0)) return PSDPROJ_ERR_INVALID_ARG;
+    if ((Lx == nullptr) != (Rx == nullptr)) return PSDPROJ_ERR_UNSUPPORTED;
+    const int es[4] = {e_l, e_r, e_c0, e_d};
+    for (int e : es)
+        if (e < -40 || e > 40) return PSDPROJ_ERR_INVALID_ARG;
+    return sym_gemm_impl(DT_F16X8, n_p, ld, L, Lx, R, Rx, C0, C0x, alpha, beta, gamma, D, Dx, es,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsdproj.so")
 
-MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4}
+MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4, "fp8_fp16_split": 5}
 DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
@@ -74,9 +74,11 @@ def lib() -> ctypes.CDLL:
     L.psdproj_tune.restype = c_int
     L.psdproj_sym_gemm.argtypes = [c_int, i64, i64, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    L.psdproj_sym_gemm_pair8.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, vp, vp, c_int, c_int, c_int, c_int, vp]
     for name in ("psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
                  "psdproj_project_batched", "psdproj_gemm_count", "psdproj_coefficients",
-                 "psdproj_release", "psdproj_sym_gemm"):
+                 "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8"):
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -213,6 +215,20 @@ def sym_gemm(dtype, L, R, D, Llo=None, Rlo=None, C0=None, C0lo=None, Dlo=None,
     _check(lib().psdproj_sym_gemm(DTYPES[dtype], n_p, ld, _ptr(L), _ptr(Llo), _ptr(R), _ptr(Rlo),
                                   _ptr(C0), _ptr(C0lo), float(alpha), float(beta), float(gamma),
                                   _ptr(D), _ptr(Dlo), _stream(stream)), "psdproj_sym_gemm")
+    return D
+
+
+def sym_gemm_pair8(L, R, D, Lx=None, Rx=None, C0=None, C0x=None, Dx=None, alpha=0.0, beta=1.0,
+                   gamma=0.0, exps=(0, 0, 0, 0), stream=None):
+    """D = alpha C0 + beta L R + gamma I on FP16 work matrices whose split
+    parts are FP8 pairs (uint8 tensors of shape (n_p, 2 ld)); exps are the
+    pair exponents of (L, R, C0, D)."""
+    n_p = L.shape[0]
+    ld = L.stride(0)
+    e = [int(v) for v in exps]
+    _check(lib().psdproj_sym_gemm_pair8(n_p, ld, _ptr(L), _ptr(Lx), _ptr(R), _ptr(Rx), _ptr(C0), _ptr(C0x),
+                                        float(alpha), float(beta), float(gamma), _ptr(D), _ptr(Dx),
+                                        e[0], e[1], e[2], e[3], _stream(stream)), "psdproj_sym_gemm_pair8")
     return D
 
 

@@ -27,3 +27,44 @@ def rel_fro(A, B):
     B = np.asarray(B, dtype=np.float64)
     nb = np.linalg.norm(B)
     return float(np.linalg.norm(A - B) / (nb if nb > 0 else 1.0))
+
+
+# e4m3 (OCP FP8: 1 sign, 4 exponent bits with bias 7, 3 mantissa bits, no
+# infinities, S.1111.111 = NaN) as a plain codec for building and reading the
+# FP8 pair buffers of the split FP8 mode.
+def e4m3_values():
+    b = np.arange(256)
+    s, e, m = b >> 7, (b >> 3) & 15, b & 7
+    v = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * 2.0 ** (e - 7.0))
+    v = np.where(s == 1, -v, v)
+    v[(e == 15) & (m == 7)] = np.nan
+    return v
+
+
+def e4m3_encode(x):
+    """Round to nearest even code after clamping to [-448, 448]."""
+    x = np.asarray(x, dtype=np.float64)
+    pos = e4m3_values()[:127]                     # codes 0x00..0x7E, increasing
+    a = np.minimum(np.abs(x), 448.0)
+    hi = np.clip(np.searchsorted(pos, a), 1, 126)  # pos[hi-1] < a <= pos[hi]
+    lo = hi - 1
+    dl, dh = a - pos[lo], pos[hi] - a
+    code = np.where(dl < dh, lo, np.where(dh < dl, hi, np.where(lo % 2 == 0, lo, hi)))
+    code = np.where(a == 0, 0, code)
+    return (code | np.where(np.signbit(x), 128, 0)).astype(np.uint8)
+
+
+def pair8_pack(hi_codes, lo_codes):
+    """(n, n) code matrices -> (n, 2 n) pair buffer: row j of the buffer is
+    column j of the matrix, rows grouped by 16 as [16 hi codes | 16 lo codes]."""
+    n = hi_codes.shape[0]
+    P = np.zeros((n, n // 16, 32), dtype=np.uint8)
+    P[:, :, :16] = hi_codes.reshape(n, n // 16, 16)
+    P[:, :, 16:] = lo_codes.reshape(n, n // 16, 16)
+    return P.reshape(n, 2 * n)
+
+
+def pair8_unpack(buf):
+    n = buf.shape[0]
+    P = buf.reshape(n, n // 16, 32)
+    return P[:, :, :16].reshape(n, n), P[:, :, 16:].reshape(n, n)

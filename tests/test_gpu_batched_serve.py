@@ -23,10 +23,10 @@ def _single(X, mode):
     return out, info_t
 
 
-@pytest.mark.parametrize("mode", ["bf16", "fp16", "fp32"])
+@pytest.mark.parametrize("mode", ["bf16", "fp16", "fp32", "fp16_split", "fp8_fp16_split"])
 def test_batched_mixed_sizes_equal_single(mode):
     import torch
-    sizes = [1, 32, 33, 100, 128, 257, 640, 1024, 1600]  # 1600 uses the 256 tile
+    sizes = [1, 32, 33, 100, 128, 257, 640, 1024, 1600]
     say("batched", mode, sizes)
     Xs = [to_dev(inputs.goe(n, 300 + n) if n > 1 else np.array([[0.7]], np.float32)) for n in sizes]
     outs = P.project_batched(Xs, mode=mode)

@@ -109,3 +109,106 @@ def test_lanczos_bound_constructed_spectrum_valid_and_tight():
     info = P.spectral_bound(to_dev(X))
     true = np.max(np.abs(np.linalg.eigvalsh(X.astype(np.float64))))
     assert true <= info["lambda"] <= 1.01 * true
+
+
+@pytest.mark.parametrize("dt,split", [("fp32", ""), ("fp16", ""), ("fp16", "R"), ("fp16", "LR"),
+                                      ("bf16", ""), ("bf16", "LR")])
+def test_sym_gemm_tile_shapes_agree(dt, split):
+    """The 128 and 256 tiles (each with its own LDS ring depth and row width)
+    give bitwise-identical products: every element accumulates its K terms in
+    the same order."""
+    import torch
+    n_p = 768
+    say("sym_gemm tiles", dt, split)
+    tdt = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[dt]
+    L = to_dev(inputs.goe(n_p, 61)).to(tdt)
+    Ll = to_dev(inputs.goe(n_p, 62)).to(tdt) if "L" in split else None
+    Rl = to_dev(inputs.goe(n_p, 63)).to(tdt) if "R" in split else None
+    outs = []
+    try:
+        for tile in (128, 256):
+            P.tune("gemm_tile", tile)
+            D = torch.zeros_like(L)
+            Dl = torch.zeros_like(L) if split else None
+            P.sym_gemm(dt, L, L, D, Llo=Ll, Rlo=Rl, C0=L, Dlo=Dl, alpha=0.5, beta=-1.25)
+            torch.cuda.synchronize()
+            outs.append((D.cpu(), Dl.cpu() if split else None))
+    finally:
+        P.tune("gemm_tile", 0)
+    assert torch.equal(outs[0][0], outs[1][0])
+    if split:
+        assert torch.equal(outs[0][1], outs[1][1])
+
+
+def _pair8(M, e):
+    """FP16 hi and the FP8 pair of a symmetric FP64 matrix; returns the device
+    tensors and the value the pair represents."""
+    from gpu_util import e4m3_encode, e4m3_values, pair8_pack
+    import torch
+    hi = M.astype(np.float16)
+    hi64 = hi.astype(np.float64)
+    hc = e4m3_encode(hi64 * 2.0 ** e)
+    lc = e4m3_encode((M - hi64) * 2.0 ** (11 + e))
+    val = hi64 + e4m3_values()[lc] * 2.0 ** -(11 + e)
+    return to_dev(hi), to_dev(pair8_pack(hc, lc)), val
+
+
+@pytest.mark.parametrize("n_p", [256, 384])
+def test_sym_gemm_pair8(n_p):
+    """FP8-pair product: L_hi R_hi + both cross terms on the e4m3 MFMA, the
+    pair addend and the pair output. Checked against the FP64 product of the
+    values the pairs represent, and the output codes bit for bit against the
+    e4m3 rounding of the stored FP16 part."""
+    import torch
+    from gpu_util import e4m3_encode, e4m3_values, pair8_unpack
+    say("sym_gemm pair8", n_p)
+    A = inputs.goe(n_p, 71, np.float64)
+    Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)          # entries up to ~2.5
+    # pair exponents keep |M| 2^e below the e4m3 maximum (448) given the
+    # spectral norms: ||A|| <= ~2, ||Bm|| <= ~9.25, ||D|| <= ~22
+    eL, eR, eC, eD = 7, 5, 7, 3
+    Lh, Lx, Lv = _pair8(A, eL)
+    Rh, Rx, Rv = _pair8(Bm, eR)
+    Ch, Cx, Cv = _pair8(A, eC)
+    D = torch.zeros_like(Lh)
+    Dx = torch.zeros(n_p, 2 * n_p, dtype=torch.uint8, device=dev())
+    P.sym_gemm_pair8(Lh, Rh, D, Lx=Lx, Rx=Rx, C0=Ch, C0x=Cx, Dx=Dx, alpha=0.5, beta=-1.25,
+                     exps=(eL, eR, eC, eD))
+    torch.cuda.synchronize()
+    Dhi = D.cpu().numpy().astype(np.float64)
+    hc, lc = pair8_unpack(Dx.cpu().numpy())
+    got = Dhi + e4m3_values()[lc] * 2.0 ** -(11 + eD)
+    ref = 0.5 * Cv + -1.25 * (Lv @ Rv)
+    err = rel_fro(got, ref)
+    plain = rel_fro((0.5 * A.astype(np.float16).astype(np.float64)
+                     - 1.25 * (A.astype(np.float16).astype(np.float64) @ Bm.astype(np.float16).astype(np.float64))
+                     ).astype(np.float16), ref)
+    say("  pair8 rel err", err, "plain fp16", plain)
+    assert err < 1.5e-4 and err < plain / 4, (err, plain)
+    np.testing.assert_array_equal(Dhi, Dhi.T)
+    np.testing.assert_array_equal(hc, hc.T)
+    np.testing.assert_array_equal(lc, lc.T)
+    tab = e4m3_values()  # compare decoded codes: -0 and +0 are one value
+    np.testing.assert_array_equal(tab[hc], tab[e4m3_encode(Dhi * 2.0 ** eD)])
+
+
+def test_sym_gemm_pair8_plain_operands_pair_output():
+    """Unsplit operands with a pair addend and a pair output (the product that
+    feeds the first split stage)."""
+    import torch
+    from gpu_util import e4m3_values, pair8_unpack
+    n_p = 256
+    say("sym_gemm pair8 plain operands")
+    A = inputs.goe(n_p, 72, np.float64)
+    Ah = A.astype(np.float16).astype(np.float64)
+    Ch, Cx, Cv = _pair8(A, 7)
+    L = to_dev(Ah.astype(np.float16))
+    D = torch.zeros_like(L)
+    Dx = torch.zeros(n_p, 2 * n_p, dtype=torch.uint8, device=dev())
+    # ||D|| <= 2 * 2 + 0.75 * 4 = 7: pair exponent 5 keeps codes below 448
+    P.sym_gemm_pair8(L, L, D, C0=Ch, C0x=Cx, Dx=Dx, alpha=2.0, beta=0.75, exps=(0, 0, 7, 5))
+    torch.cuda.synchronize()
+    hc, lc = pair8_unpack(Dx.cpu().numpy())
+    got = D.cpu().numpy().astype(np.float64) + e4m3_values()[lc] * 2.0 ** -16
+    ref = 2.0 * Cv + 0.75 * (Ah @ Ah)
+    assert rel_fro(got, ref) < 5e-5, rel_fro(got, ref)

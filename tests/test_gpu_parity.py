@@ -18,7 +18,8 @@ from gpu_util import dev, rel_fro, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL_POLY = {"fp32": 1e-5, "fp32_emu": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "bf16": 3e-2}
+TOL_POLY = {"fp32": 1e-5, "fp32_emu": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "fp8_fp16_split": 5e-3,
+            "bf16": 3e-2}
 
 
 def _run(X32, mode, **opts):
@@ -54,17 +55,38 @@ def test_c1_fp32_n256():
     assert rel_fro(out, exact) < 2e-5
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp32", "fp32_emu"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp32", "fp32_emu"])
 @pytest.mark.parametrize("n", [200, 777])
 def test_goe_ragged(mode, n):
     X32 = inputs.goe(n, 2)
     exact = oracle.project_exact_eigh(X32.astype(np.float64))
     out, _ = _check_case("goe", X32, mode, exact)
-    if mode == "fp16_split":
+    if mode in ("fp16_split", "fp8_fp16_split"):
         assert rel_fro(out, exact) <= 1e-3
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split"])
+def test_fp8_pairs_against_fp16_pairs():
+    """FP8 pairs carry the split correction to ~2^-15 relative (an e4m3 code,
+    2^-4 accurate, of a 2^-11 residual) where FP16 lo halves reach ~2^-22.
+    With every stage and the final product split, FP8 pairs land an order of
+    magnitude below plain FP16 and within a small factor of FP16 pairs, whose
+    error is then the polynomial's own (~3.6e-5 on this spectrum)."""
+    X32 = inputs.goe(777, 2)
+    X = X32.astype(np.float64)
+    exact = oracle.project_exact_eigh(X)
+    errs = {}
+    for mode in ("fp16", "fp16_split", "fp8_fp16_split"):
+        opts = {} if mode == "fp16" else dict(split_mask=0x7F, split_final=1)
+        out, info = _run(X32, mode, **opts)
+        errs[mode] = rel_fro(out, exact)
+        ref, _ = oracle.project_poly(X, "fp16", lam=info["lambda"])
+        assert rel_fro(out, ref) <= 5e-3
+    say("  all-split errors vs exact", errs)
+    assert errs["fp8_fp16_split"] <= 3.0 * errs["fp16_split"]
+    assert errs["fp8_fp16_split"] <= errs["fp16"] / 8
+
+
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split"])
 def test_clustered_n1000(mode):
     X32, Q, lam = inputs.clustered(1000, 3)
     exact = oracle.project_spectral(Q, lam, lambda l: np.maximum(l, 0.0))
@@ -74,7 +96,7 @@ def test_clustered_n1000(mode):
 def test_lowrank_noise_n640():
     X32 = inputs.lowrank_noise(640, 5, 6, rank=32)
     exact = oracle.project_exact_eigh(X32.astype(np.float64))
-    for mode in ("fp16", "fp16_split"):
+    for mode in ("fp16", "fp16_split", "fp8_fp16_split"):
         _check_case("lowrank", X32, mode, exact)
 
 

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, nm), nm
 
 
-@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu"])
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu", "fp8_fp16_split"])
 def test_library_coefficients_match_oracle(mode):
     lib_rows = P.coefficients(mode)
     ora_rows = oracle.stage_rows(mode)
@@ -47,6 +47,10 @@ def test_gemm_counts():
     assert P.gemm_count("fp32_emu") == 93  # 10 stages x 3 split products x 3 + 3
     # split products cost 2-3 GEMMs each: no split stages, split final only
     assert P.gemm_count("fp16_split", split_mask=0, split_final=1) >= 22
+    # a split product: 3 FP16 products with FP16 lo halves, 2 with FP8 pairs
+    assert P.gemm_count("fp16_split", split_mask=0x6, split_final=0) == 22 + 6 * 2
+    assert P.gemm_count("fp8_fp16_split", split_mask=0x6, split_final=0) == 22 + 6
+    assert P.gemm_count("fp8_fp16_split", split_mask=0x7F, split_final=1) == 44
 
 
 def test_workspace_bytes_grow_with_n():
@@ -68,6 +72,12 @@ def test_invalid_arguments_rejected_before_device_work():
     assert L.psdproj_project_ex(ctypes.byref(o), 5, 5, vp(16), vp(16), None, None) == 1
     assert L.psdproj_sym_gemm(1, 100, 100, vp(16), None, vp(16), None, None, None,
                               0.0, 1.0, 0.0, vp(16), None, None) == 1  # n_p % 128
+    assert L.psdproj_sym_gemm_pair8(100, 100, vp(16), None, vp(16), None, None, None,
+                                    0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 0, None) == 1  # n_p % 128
+    assert L.psdproj_sym_gemm_pair8(128, 128, vp(16), vp(16), vp(16), None, None, None,
+                                    0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 0, None) == 2  # one-sided pair
+    assert L.psdproj_sym_gemm_pair8(128, 128, vp(16), None, vp(16), None, None, None,
+                                    0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 99, None) == 1  # exponent range
 
 
 def test_status_strings():
