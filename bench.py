@@ -28,8 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ms per n=10k PSD projection at ≤1e-3 rel err; batched proj/s + p99 latency"
-PEAK = {"fp16": 2.5e15, "bf16": 2.5e15, "fp16_split": 2.5e15, "fp32": 157.3e12}
-DTYPE_NAME = {"fp16": "fp16", "bf16": "bf16", "fp16_split": "fp16", "fp32": "fp32"}
+PEAK = {"fp16": 2.5e15, "bf16": 2.5e15, "fp16_split": 2.5e15, "fp8_fp16_split": 2.5e15, "fp32_emu": 2.5e15,
+        "fp32": 157.3e12}
+DTYPE_NAME = {"fp16": "fp16", "bf16": "bf16", "fp16_split": "fp16", "fp8_fp16_split": "fp16+fp8",
+              "fp32_emu": "fp16", "fp32": "fp32"}
 
 
 def log(*a):
@@ -77,33 +79,45 @@ def time_rocsolver(rs, X, dtype, reps=1):
 
 # ---------------------------------------------------------------------------
 def gemm_roofline(n, mode, reps=10):
-    """Average duration of one symmetric stage GEMM launch (B = b A + c A A with
-    its fused epilogue) at the padded size of n, timed with HIP events on the
-    launch stream; achieved = algorithmic n^2 (n + 1) flops / duration."""
+    """Average duration of one symmetric stage GEMM launch (A = X0 X0 with the
+    stage epilogue, on an X0-like operand: a GOE matrix over its bound 2, in
+    the mode's FP16 storage) at the padded size of n, the kernel instantiation
+    the projection's plain stages run, timed with HIP events around `reps`
+    back-to-back launches on the launch stream. achieved = algorithmic
+    n^2 (n + 1) flops (the upper triangle of an n x n product) / duration."""
     import torch
     from paper_2507_09165_amd import psdproj as P
-    dt = "fp32" if mode == "fp32" else ("bf16" if mode == "bf16" else "fp16")
+    dt = "fp32" if mode in ("fp32",) else ("bf16" if mode == "bf16" else "fp16")
     tdt = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[dt]
     n_p = (n + 127) // 128 * 128
     g = torch.Generator(device="cuda").manual_seed(1)
-    A = (torch.rand(n_p, n_p, device="cuda", generator=g) - 0.5) * (2.0 / np.sqrt(n_p))
-    A = ((A + A.t()) * 0.5).to(tdt)
+    G = torch.randn(n_p, n_p, device="cuda", generator=g)
+    A = ((G + G.t()) * (0.5 / np.sqrt(2.0 * n_p))).to(tdt)
+    del G
     D = torch.empty_like(A)
     st = torch.cuda.current_stream()
+    if mode == "fp8_fp16_split":
+        def launch():
+            P.sym_gemm_pair8(A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+        kernel = "gemm_sym_kernel<f16, plain operands, FP8-pair storage, stage epilogue>"
+    else:
+        def launch():
+            P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+        kernel = f"gemm_sym_kernel<{dt}, stage epilogue>"
     for _ in range(2):
-        P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+        launch()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(st)
     for _ in range(reps):
-        P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
+        launch()
     ev1.record(st)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     flops = float(n) * n * (n + 1)
     achieved = flops / (ms * 1e-3)
     peak = PEAK[mode]
-    return {"kernel": f"gemm_sym_kernel<{dt}, stage epilogue>", "bound": "mfma", "achieved": achieved / 1e12,
+    return {"kernel": kernel, "bound": "mfma", "achieved": achieved / 1e12,
             "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
             "ms_per_launch": ms, "flops_per_launch": flops, "n_padded": n_p}
 
@@ -230,7 +244,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10000)
-    ap.add_argument("--mode", default="fp16_split", choices=["fp16", "bf16", "fp16_split", "fp32"])
+    ap.add_argument("--mode", default="fp16_split", choices=sorted(PEAK))
     ap.add_argument("--input", default="goe", choices=["goe", "lowrank"])
     ap.add_argument("--split-mask", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--cpu-sample", type=int, default=4096)

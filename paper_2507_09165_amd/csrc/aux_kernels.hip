@@ -140,9 +140,19 @@ enum SymvDst { DST_U = 0, DST_W = 1, DST_W2 = 2 };
 // and y_k = sum_{I <= K} d[tile(I, K)][k] + sum_{J >= K} a[tile(K, J)][k],
 // summed in that fixed order by symv_reduce_kernel. With NORMS the same is
 // done for X(i, j)^2 and v = 1, which yields the full column norms.
+//
+// The kernel is bound by reading the triangle: every thread issues all 16 of
+// its 16-byte loads (a quarter column of 4 rows x 16 columns) before any
+// arithmetic, so a workgroup keeps the whole 64 KB tile in flight. A
+// half-wave covers one 512-byte column segment per load. Row sums reduce the
+// 8 column groups through LDS; column dots reduce the 32 row quads through
+// LDS, both in a fixed order.
 template <bool NORMS>
 __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
                                                         IoArg io0, int src, int jstep, int stop_on_flag) {
+    constexpr int NQ = kTB / 4;         // row quads per column (32)
+    constexpr int NG = 256 / NQ;        // column groups (8)
+    constexpr int NL = kTB / NG;        // columns per thread (16)
     const WorkItem wi = W[blockIdx.x];
     const MatDesc &dm = D[wi.x];
     if (stop_on_flag && dm.scal->stop) return;
@@ -156,56 +166,87 @@ __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const 
     const double *v = src == SRC_V ? dm.V + (int64_t)jstep * n : (src == SRC_W ? dm.w : dm.u);
     const double sc = src == SRC_QHAT ? dm.scal->qnorm_inv : 1.0;
     __shared__ double vI[kTB], vJ[kTB];
-    __shared__ double red[4][kTB], red2[4][kTB];
-    if (threadIdx.x < kTB) {
-        const int64_t i = i0 + threadIdx.x;
-        vI[threadIdx.x] = i < n ? v[i] * sc : 0.0;
+    __shared__ double cpart[NORMS ? 2 : 1][kTB][NQ + 1];  // column dots per row quad (padded)
+    __shared__ double rpart[NORMS ? 2 : 1][NG][kTB];      // row sums per column group
+    const int tid = threadIdx.x;
+    const int q = tid % NQ, grp = tid / NQ;  // row quad, column group
+    const int64_t ir = i0 + 4 * q;           // first row of the quad
+
+    // loads first: column grp + NG k of the tile, rows ir .. ir + 3
+    f32x4 x[NL];
+    const bool vec = ((reinterpret_cast<uintptr_t>(io.X) & 15) == 0) && ((io.ld & 3) == 0);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int64_t j = j0 + grp + NG * k;
+        const float *col = io.X + j * io.ld;
+        if (j < n && vec && ir + 3 < n && (!diag || ir + 3 <= j)) {
+            x[k] = *(const f32x4 *)(col + ir);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = ir + e;
+                x[k][e] = (j < n && i < n && (!diag || i <= j)) ? col[i] : 0.0f;
+            }
+        }
+    }
+    if (tid < kTB) {
+        const int64_t i = i0 + tid;
+        vI[tid] = i < n ? v[i] * sc : 0.0;
     } else {
-        const int64_t j = j0 + threadIdx.x - kTB;
-        vJ[threadIdx.x - kTB] = j < n ? v[j] * sc : 0.0;
+        const int64_t j = j0 + tid - kTB;
+        vJ[tid - kTB] = j < n ? v[j] * sc : 0.0;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = 2 * lane;  // this lane's two rows of the tile
-    const int64_t ia = i0 + r0, ib = ia + 1;
-    double ax0 = 0.0, ax1 = 0.0, sq0 = 0.0, sq1 = 0.0;
-    const double via = vI[r0], vib = vI[r0 + 1];
-    double *dd = dm.sd + (int64_t)t * kTB;
-#pragma unroll 8
-    for (int cc = 0; cc < 32; ++cc) {  // wave w handles tile columns 32 w .. 32 w + 31
-        const int c = 32 * wave + cc;
+    double va[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) va[e] = vI[4 * q + e];
+    double ra[4] = {0.0, 0.0, 0.0, 0.0}, rq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int c = grp + NG * k;
         const int64_t j = j0 + c;
-        float x0 = 0.0f, x1 = 0.0f;
-        if (j < n) {
-            const float *col = io.X + j * io.ld;
-            if (ia < n && (!diag || ia <= j)) x0 = col[ia];
-            if (ib < n && (!diag || ib <= j)) x1 = col[ib];
-        }
-        const double dot = wave_sum((double)x0 * via + (double)x1 * vib);
         const double vj = vJ[c];
-        // row sums: strictly upper entries only (the diagonal is in the dot)
-        const bool u0 = !diag || ia < j, u1 = !diag || ib < j;
-        ax0 += u0 ? (double)x0 * vj : 0.0;
-        ax1 += u1 ? (double)x1 * vj : 0.0;
-        if (lane == 0) dd[c] = dot;
-        if constexpr (NORMS) {
-            const double q = wave_sum((double)x0 * x0 + (double)x1 * x1);
-            sq0 += u0 ? (double)x0 * x0 : 0.0;
-            sq1 += u1 ? (double)x1 * x1 : 0.0;
-            if (lane == 0) dm.sd2[(int64_t)t * kTB + c] = q;
+        double dot = 0.0, sq = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double xe = (double)x[k][e];
+            dot += xe * va[e];
+            // row sums: strictly upper entries only (the diagonal is in the dot)
+            const bool up = !diag || ir + e < j;
+            ra[e] += up ? xe * vj : 0.0;
+            if constexpr (NORMS) {
+                sq += xe * xe;
+                rq[e] += up ? xe * xe : 0.0;
+            }
         }
+        cpart[0][c][q] = dot;
+        if constexpr (NORMS) cpart[NORMS ? 1 : 0][c][q] = sq;
     }
-    red[wave][r0] = ax0;
-    red[wave][r0 + 1] = ax1;
-    if constexpr (NORMS) {
-        red2[wave][r0] = sq0;
-        red2[wave][r0 + 1] = sq1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        rpart[0][grp][4 * q + e] = ra[e];
+        if constexpr (NORMS) rpart[NORMS ? 1 : 0][grp][4 * q + e] = rq[e];
     }
     __syncthreads();
-    if (threadIdx.x < kTB) {
-        const int r = threadIdx.x;
-        dm.sa[(int64_t)t * kTB + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
-        if constexpr (NORMS) dm.sa2[(int64_t)t * kTB + r] = red2[0][r] + red2[1][r] + red2[2][r] + red2[3][r];
+    const int64_t base = (int64_t)t * kTB;
+    if (tid < kTB) {
+        double d = 0.0, d2 = 0.0;
+        for (int k = 0; k < NQ; ++k) {
+            d += cpart[0][tid][k];
+            if constexpr (NORMS) d2 += cpart[NORMS ? 1 : 0][tid][k];
+        }
+        dm.sd[base + tid] = d;
+        if constexpr (NORMS) dm.sd2[base + tid] = d2;
+    } else {
+        const int r = tid - kTB;
+        double a = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            a += rpart[0][g][r];
+            if constexpr (NORMS) a2 += rpart[NORMS ? 1 : 0][g][r];
+        }
+        dm.sa[base + r] = a;
+        if constexpr (NORMS) dm.sa2[base + r] = a2;
     }
 }
 
