@@ -9,9 +9,10 @@ final combine, in the chosen precision form.
 
 Printed (one JSON line): ms per projection, its relative error against an
 FP64 eigen-projection (rocSOLVER dsyevd on the same GPU), the roofline of the
-dominant kernel (the symmetric FP16 stage GEMM, timed with HIP events on its
-stream), the rocSOLVER ssyevd/dsyevd projection times, and the FP64 CPU oracle
-timed on a bounded sample and scaled to n = 10,000 by n^3.
+dominant kernel (the plain symmetric stage GEMM, its launches inside one more
+projection bracketed by HIP events on the projection's stream), the rocSOLVER
+ssyevd/dsyevd projection times, and the FP64 CPU oracle timed on a bounded
+sample and scaled to n = 10,000 by n^3.
 """
 from __future__ import annotations
 
@@ -78,48 +79,31 @@ def time_rocsolver(rs, X, dtype, reps=1):
 
 
 # ---------------------------------------------------------------------------
-def gemm_roofline(n, mode, reps=10):
-    """Average duration of one symmetric stage GEMM launch (A = X0 X0 with the
-    stage epilogue, on an X0-like operand: a GOE matrix over its bound 2, in
-    the mode's FP16 storage) at the padded size of n, the kernel instantiation
-    the projection's plain stages run, timed with HIP events around `reps`
-    back-to-back launches on the launch stream. achieved = algorithmic
-    n^2 (n + 1) flops (the upper triangle of an n x n product) / duration."""
+def gemm_roofline(X, out, opts, n, mode, stream):
+    """Roofline of the dominant kernel, the plain symmetric stage GEMM, measured
+    on the projection's own launches: one more projection runs with every
+    filter product bracketed by HIP events on its stream; achieved = the
+    algorithmic n^2 (n + 1) flops of one product (the upper triangle of an
+    n x n product) / the average event time of the plain stage products.
+    The other product classes are reported beside it."""
     import torch
     from paper_2507_09165_amd import psdproj as P
-    dt = "fp32" if mode in ("fp32",) else ("bf16" if mode == "bf16" else "fp16")
-    tdt = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[dt]
-    n_p = (n + 127) // 128 * 128
-    g = torch.Generator(device="cuda").manual_seed(1)
-    G = torch.randn(n_p, n_p, device="cuda", generator=g)
-    A = ((G + G.t()) * (0.5 / np.sqrt(2.0 * n_p))).to(tdt)
-    del G
-    D = torch.empty_like(A)
-    st = torch.cuda.current_stream()
-    if mode == "fp8_fp16_split":
-        def launch():
-            P.sym_gemm_pair8(A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
-        kernel = "gemm_sym_kernel<f16, plain operands, FP8-pair storage, stage epilogue>"
-    else:
-        def launch():
-            P.sym_gemm(dt, A, A, D, C0=A, alpha=-1.2, beta=0.5, stream=st)
-        kernel = f"gemm_sym_kernel<{dt}, stage epilogue>"
-    for _ in range(2):
-        launch()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    P.gemm_timing_start()
+    P.project_ex(X, out, stream=stream, info=False, **opts)
+    cls = P.gemm_timing_stop()
     torch.cuda.synchronize()
-    ev0.record(st)
-    for _ in range(reps):
-        launch()
-    ev1.record(st)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+    ms = cls["plain"]["avg_ms"]
     flops = float(n) * n * (n + 1)
     achieved = flops / (ms * 1e-3)
     peak = PEAK[mode]
-    return {"kernel": kernel, "bound": "mfma", "achieved": achieved / 1e12,
-            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-            "ms_per_launch": ms, "flops_per_launch": flops, "n_padded": n_p}
+    dt = DTYPE_NAME[mode]
+    classes = {k: v for k, v in cls.items() if v["launches"]}
+    for v in classes.values():
+        v["tflops_per_product_equivalent"] = flops / (v["avg_ms"] * 1e-3) / 1e12
+    return {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection launches)", "bound": "mfma",
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "ms_per_launch": ms, "flops_per_launch": flops, "launches": cls["plain"]["launches"],
+            "n_padded": (n + 127) // 128 * 128, "product_classes": classes}
 
 
 def cpu_baseline(mode, n_sample):
@@ -134,7 +118,7 @@ def cpu_baseline(mode, n_sample):
         cores = os.cpu_count() or 1
     X = inputs.goe(n_sample, 4).astype(np.float64)
     t0 = time.perf_counter()
-    oracle.project_poly(X, mode if mode != "fp16_split" else "fp16")
+    oracle.project_poly(X, mode)
     dt = time.perf_counter() - t0
     scale = (10000.0 / n_sample) ** 3
     return {"value": dt * 1e3 * scale, "unit": "ms", "cores": cores, "kind": "oracle",
@@ -175,7 +159,7 @@ def serving_leg(num=600, rho=(0.8,), clients=8, slots=4, seed=11):
     """Poisson arrivals at rho * mu (mu: measured saturated throughput) of
     requests from `clients` ADMM-like iterate streams (n log-uniform in
     [64, 8192]; Y_k = Y_{k-1} + sqrt(1e-3) GOE_k, 8 iterates per client kept
-    in HBM), target 1e-3 (FP16_SPLIT) or 1e-5 (FP32) drawn 70/30; admitted
+    in HBM), target 1e-3 (FP8_FP16_SPLIT) or 1e-5 (FP32) drawn 70/30; admitted
     under a 200 GB budget. Reports p50/p99 latency and projections/s."""
     import threading
     import torch
@@ -244,7 +228,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10000)
-    ap.add_argument("--mode", default="fp16_split", choices=sorted(PEAK))
+    ap.add_argument("--mode", default="fp8_fp16_split", choices=sorted(PEAK))
     ap.add_argument("--input", default="goe", choices=["goe", "lowrank"])
     ap.add_argument("--split-mask", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--cpu-sample", type=int, default=4096)
@@ -310,7 +294,7 @@ def main():
     res["algorithmic_tflops"] = flops / (ms * 1e-3) / 1e12
 
     log("gemm roofline")
-    res["roofline"] = gemm_roofline(n, args.mode)
+    res["roofline"] = gemm_roofline(X, out, opts, n, args.mode, st)
 
     if not args.no_rocsolver or not args.no_check:
         rs = RocSolver(st)

@@ -179,7 +179,7 @@ typedef struct {
     const float *X;  /* device, upper triangle read */
     float *out;      /* device */
     double target;   /* accuracy target when mode < 0: <= 1e-4 -> FP32,
-                        otherwise FP16_SPLIT */
+                        otherwise FP8_FP16_SPLIT */
     int mode;        /* psdproj_mode, or -1 to choose from target */
     uint64_t tag;    /* caller's tag, echoed in the result */
 } psdproj_request;
@@ -215,6 +215,30 @@ int psdproj_serve_cancel(psdproj_server *s, uint64_t ticket);
 int psdproj_serve_stats(psdproj_server *s, psdproj_serve_statistics *st);
 /* Drain running work, cancel queued requests, free streams and workspaces. */
 int psdproj_serve_destroy(psdproj_server *s);
+
+/* ---- product timing (tooling) ---------------------------------------------
+ * psdproj_gemm_timing_start clears earlier records and brackets the launches
+ * of every filter product of later projections (any stream, the device
+ * current at the call) with two HIP events. psdproj_gemm_timing_stop stops
+ * recording, waits for the recorded events and returns per product class
+ * (index below, out[cap]) the number of products and their summed event time
+ * in ms. The events add no device work; a product of a batched projection is
+ * one bracket around all its matrices. */
+enum {
+    PSDPROJ_GEMM_PLAIN = 0,           /* unsplit operands, work-precision output */
+    PSDPROJ_GEMM_PLAIN_SPLIT_OUT = 1, /* unsplit operands, split output          */
+    PSDPROJ_GEMM_PAIR = 2,            /* split operands, work-precision output   */
+    PSDPROJ_GEMM_PAIR_SPLIT_OUT = 3,  /* split operands, split output            */
+    PSDPROJ_GEMM_FINAL = 4,           /* final product, unsplit                  */
+    PSDPROJ_GEMM_PAIR_FINAL = 5,      /* final product, split                    */
+    PSDPROJ_GEMM_CLASSES = 6
+};
+typedef struct {
+    int64_t launches;
+    double total_ms;
+} psdproj_gemm_timing_entry;
+int psdproj_gemm_timing_start(void);
+int psdproj_gemm_timing_stop(psdproj_gemm_timing_entry *out, int cap);
 
 /* ---- kernel-level entry points (used by tests and tooling) ---------------
  * psdproj_sym_gemm: D = alpha C0 + beta (L R) + gamma I on n_p x n_p

@@ -47,8 +47,11 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *sh /* [4][
 }
 
 // Sum of the per-block partials part[b * stride + k], b = 0..nb-1, in order.
+// (Unrolled so that the loads of several partials are in flight at once; the
+// additions stay in order.)
 __device__ __forceinline__ double sum_partials(const double *part, int nb, int stride, int k) {
     double s = 0.0;
+#pragma unroll 8
     for (int b = 0; b < nb; ++b) s += part[(int64_t)b * stride + k];
     return s;
 }
@@ -269,10 +272,12 @@ __global__ __launch_bounds__(256) void symv_reduce_kernel(const MatDesc *D, cons
     if (k < n) {
         const int K = (int)(k / kTB), kk = (int)(k % kTB);
         const int64_t base = (int64_t)K * (K + 1) / 2;
+#pragma unroll 8
         for (int I = 0; I <= K; ++I) {
             yk += dm.sd[(base + I) * kTB + kk];
             if constexpr (NORMS) ck += dm.sd2[(base + I) * kTB + kk];
         }
+#pragma unroll 8
         for (int J = K; J < T; ++J) {
             const int64_t t = (int64_t)J * (J + 1) / 2 + K;
             yk += dm.sa[t * kTB + kk];
@@ -346,6 +351,7 @@ __global__ __launch_bounds__(256) void lz_orth_kernel(const MatDesc *D, const Wo
     }
     if (i < n) {
         double s = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= j; ++k) s += dm.V[(int64_t)k * n + i] * hsh[k];
         wi_ -= s;
         dm.w[i] = wi_;

@@ -288,6 +288,35 @@ __global__ void info_kernel(const MatDesc *D, psdproj_info *info, int stages) {
     info->stages = stages;
 }
 
+// Optional event timing of the filter products (psdproj_gemm_timing_*): each
+// product's launches are bracketed by two HIP events on the projection's
+// stream, tagged with the product's class. Guarded by g_mu like the plans.
+struct GemmTimer {
+    bool on = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+};
+GemmTimer g_timer;
+
+int gemm_class(bool split_operands, int epi) {
+    if (epi == EPI_FINAL) return PSDPROJ_GEMM_FINAL + (split_operands ? 1 : 0);
+    return (split_operands ? PSDPROJ_GEMM_PAIR : PSDPROJ_GEMM_PLAIN) + (epi == EPI_STORE_SPLIT ? 1 : 0);
+}
+
 // Enqueue the whole sequence for the plan's matrices. ios: host array of the
 // caller's I/O, one per matrix.
 int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, psdproj_info *info, bool bound_only) {
@@ -344,6 +373,10 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         g.sl = sl; g.sr = sr; g.sc0 = sc0; g.sd = sd; g.c0_split = c0s ? 1 : 0;
         g.alpha = alpha; g.beta = beta; g.gamma = gamma;
         g.es_l = slot_e[sl]; g.es_r = slot_e[sr]; g.es_c0 = sc0 >= 0 ? slot_e[sc0] : 0; g.es_d = e_out;
+        GemmTimer::Rec rec{gemm_class(ls || rs, epi), nullptr, nullptr};
+        if (g_timer.on && (rec.a = g_timer.take()) && (rec.b = g_timer.take())) {
+            if (hipEventRecord(rec.a, s) != hipSuccess) return hipErrorUnknown;
+        }
         for (int c = 0; c < 2; ++c) {
             if (!P.n_gemm[c]) continue;
             g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
@@ -351,6 +384,10 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
             if (r != hipSuccess) return r;
         }
         if (epi != EPI_FINAL) slot_e[sd] = e_out;
+        if (rec.b) {
+            if (hipEventRecord(rec.b, s) != hipSuccess) return hipErrorUnknown;
+            g_timer.pending.push_back(rec);
+        }
         return hipSuccess;
     };
     // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
@@ -592,11 +629,50 @@ int psdproj_release(void) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     }
     g_pool.clear();
+    for (auto &r : g_timer.pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_timer.pending.clear();
+    for (hipEvent_t e : g_timer.pool) (void)hipEventDestroy(e);
+    g_timer.pool.clear();
     std::lock_guard<std::mutex> lk2(g_sg_mu);
     for (auto &kv : g_sg)
         if (kv.second.buf) (void)hipFree(kv.second.buf);
     g_sg.clear();
     return PSDPROJ_OK;
+}
+
+int psdproj_gemm_timing_start(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &r : g_timer.pending) {
+        (void)hipEventSynchronize(r.b);
+        g_timer.pool.push_back(r.a);
+        g_timer.pool.push_back(r.b);
+    }
+    g_timer.pending.clear();
+    g_timer.on = true;
+    return PSDPROJ_OK;
+}
+
+int psdproj_gemm_timing_stop(psdproj_gemm_timing_entry *out, int cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_timer.on = false;
+    psdproj_gemm_timing_entry acc[PSDPROJ_GEMM_CLASSES] = {};
+    int status = PSDPROJ_OK;
+    for (auto &r : g_timer.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            status = PSDPROJ_ERR_HIP;
+        acc[r.cls].launches += 1;
+        acc[r.cls].total_ms += ms;
+        g_timer.pool.push_back(r.a);
+        g_timer.pool.push_back(r.b);
+    }
+    g_timer.pending.clear();
+    if (out)
+        for (int c = 0; c < cap && c < PSDPROJ_GEMM_CLASSES; ++c) out[c] = acc[c];
+    return status;
 }
 
 int psdproj_tune(const char *key, int64_t value) {

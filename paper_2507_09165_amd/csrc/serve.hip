@@ -93,7 +93,7 @@ struct psdproj_server {
 
 static int choose_mode(const psdproj_request &r) {
     if (r.mode >= 0) return r.mode;
-    return r.target <= 1e-4 ? PSDPROJ_MODE_FP32 : PSDPROJ_MODE_FP16_SPLIT;
+    return r.target <= 1e-4 ? PSDPROJ_MODE_FP32 : PSDPROJ_MODE_FP8_FP16_SPLIT;
 }
 
 // Pick a free slot for a request of `ws` bytes: prefer the smallest pool that

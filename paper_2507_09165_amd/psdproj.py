@@ -76,7 +76,10 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     L.psdproj_sym_gemm_pair8.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float, vp, vp, c_int, c_int, c_int, c_int, vp]
-    for name in ("psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
+    L.psdproj_gemm_timing_start.argtypes = []
+    L.psdproj_gemm_timing_stop.argtypes = [ctypes.c_void_p, c_int]
+    for name in ("psdproj_gemm_timing_start", "psdproj_gemm_timing_stop",
+                 "psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
                  "psdproj_project_batched", "psdproj_gemm_count", "psdproj_coefficients",
                  "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8"):
         getattr(L, name).restype = c_int
@@ -230,6 +233,29 @@ def sym_gemm_pair8(L, R, D, Lx=None, Rx=None, C0=None, C0x=None, Dx=None, alpha=
                                         float(alpha), float(beta), float(gamma), _ptr(D), _ptr(Dx),
                                         e[0], e[1], e[2], e[3], _stream(stream)), "psdproj_sym_gemm_pair8")
     return D
+
+
+GEMM_CLASSES = ("plain", "plain_split_out", "pair", "pair_split_out", "final", "pair_final")
+
+
+class _TimingEntry(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+def gemm_timing_start():
+    """Bracket every filter product of later projections with HIP events."""
+    _check(lib().psdproj_gemm_timing_start(), "psdproj_gemm_timing_start")
+
+
+def gemm_timing_stop():
+    """Stop, wait for the recorded events, and return
+    {class: {"launches": k, "total_ms": t, "avg_ms": t / k}}."""
+    arr = (_TimingEntry * len(GEMM_CLASSES))()
+    _check(lib().psdproj_gemm_timing_stop(ctypes.cast(arr, ctypes.c_void_p), len(GEMM_CLASSES)),
+           "psdproj_gemm_timing_stop")
+    return {name: {"launches": int(e.launches), "total_ms": float(e.total_ms),
+                   "avg_ms": float(e.total_ms) / e.launches if e.launches else None}
+            for name, e in zip(GEMM_CLASSES, arr)}
 
 
 # ---------------------------------------------------------------------------

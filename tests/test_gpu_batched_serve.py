@@ -68,7 +68,7 @@ def test_served_results_equal_alone():
     sizes = [64, 300, 1000, 2100, 129, 777, 64, 1500]
     targets = [1e-3, 1e-5, 1e-3, 1e-3, 1e-5, 1e-3, 1e-3, 1e-5]
     Xs = [to_dev(inputs.goe(n, 500 + i)) for i, n in enumerate(sizes)]
-    modes = ["fp32" if t <= 1e-4 else "fp16_split" for t in targets]
+    modes = ["fp32" if t <= 1e-4 else "fp8_fp16_split" for t in targets]
     alone = [P.project(X, mode=m) for X, m in zip(Xs, modes)]
     torch.cuda.synchronize()
     outs = [torch.full_like(X, float("nan")) for X in Xs]

@@ -130,4 +130,4 @@ def test_mode_from_target():
         a = s.submit(n=100, target=1e-5)
         b = s.submit(n=100, target=1e-3)
         assert s.wait(a, 10)["mode"] == 0      # FP32
-        assert s.wait(b, 10)["mode"] == 3      # FP16_SPLIT
+        assert s.wait(b, 10)["mode"] == 5      # FP8_FP16_SPLIT
