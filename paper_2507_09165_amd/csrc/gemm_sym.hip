@@ -94,16 +94,19 @@ constexpr int kThreads = 256;  // 4 waves in a 2 x 2 layout
 typedef __attribute__((address_space(1))) void *gptr_t;
 typedef __attribute__((address_space(3))) void *lptr_t;
 
-// 16-byte chunk c of LDS row r is stored at chunk position swz(r, c). The
-// fragment reads of one ds_read_b128 take rows r..r+31 at one logical chunk;
-// gfx950 serves 16 lanes per cycle from 64 banks, so any 16 consecutive rows
-// (and any 8) must land on distinct 16-byte bank groups. XOR with a key that
-// changes with both r and r / 8 does that for 128-byte and 64-byte rows.
+// 16-byte chunk c of LDS row r is stored at chunk position swz(r, c) (an XOR,
+// so the same map places and finds a chunk). The fragment reads of one
+// ds_read_b128 take rows r..r+31 at one logical chunk per lane half. The keys
+// were chosen by measuring LDS bank-conflict cycles of exactly these read
+// patterns on gfx950: with 128-byte rows, keying on r / 2 (row pairs share a
+// key, the pair's two rows fill the two 32-bank halves) gives the ideal 4
+// cycles per read, where keys that differ within a row pair cost 8; with
+// 64-byte rows, keying on r / 4 gives 6.7 cycles against 8.
 template <int NCH>
 __device__ __forceinline__ int swz(int r, int c) {
-    if constexpr (NCH == 8) return c ^ ((r + (r >> 3)) & 7);
-    else if constexpr (NCH == 4) return c ^ (((r >> 1) + (r >> 3)) & 3);
-    else return c ^ (((r >> 2) ^ (r >> 3)) & 1);
+    if constexpr (NCH == 8) return c ^ ((r >> 1) & 7);
+    else if constexpr (NCH == 4) return c ^ ((r >> 2) & 3);
+    else return c ^ ((r >> 3) & 1);
 }
 
 // vmcnt-only wait (expcnt and lgkmcnt left unconstrained), gfx9 encoding.
@@ -467,8 +470,11 @@ int64_t gemm_padded_size(int64_t n) {
 // stages within 80 KB, so two workgroups share a CU (160 KB of LDS) whether or
 // not the operands are split: plain panels get 128-byte rows, split panels
 // 64-byte rows (measured 1.7% faster per split projection than one 128-KB
-// workgroup per CU). The 256 tile uses 128 KB: a 4-stage ring for plain
-// operands, two stages of 64-byte rows for split ones.
+// workgroup per CU). Deeper rings measured slower at n = 10^4 for the plain
+// product (1.20 ms per product with this ring; 1.36-1.52 ms with 3-5 stages of
+// 64- or 128-byte rows at one or two workgroups per CU). The 256 tile uses
+// 128 KB: a 4-stage ring for plain operands, two stages of 64-byte rows for
+// split ones.
 template <int BM, int NP> struct LdsCfg {
     static constexpr int NST = (BM == 256 && NP == 2) ? 4 : 2;
     static constexpr int BUDGET = BM == 256 ? 128 * 1024 : 80 * 1024;
