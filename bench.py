@@ -79,6 +79,26 @@ def time_rocsolver(rs, X, dtype, reps=1):
 
 
 # ---------------------------------------------------------------------------
+def measured_traffic(kernel_mode):
+    """HBM bytes per launch of the plain stage product from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same
+    counter on a device copy of known size), or None when the summary is for
+    another mode or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_plain_n10000_traffic.json")
+    if kernel_mode != "fp8_fp16_split" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.md5()
+    for src in rec["kernel_sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["kernel_sources_md5"]:
+        return None
+    return rec
+
+
 def gemm_roofline(X, out, opts, n, mode, stream):
     """Roofline of the dominant kernel, the plain symmetric stage GEMM, measured
     on the projection's own launches: one more projection runs with every
@@ -100,10 +120,17 @@ def gemm_roofline(X, out, opts, n, mode, stream):
     classes = {k: v for k, v in cls.items() if v["launches"]}
     for v in classes.values():
         v["tflops_per_product_equivalent"] = flops / (v["avg_ms"] * 1e-3) / 1e12
-    return {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection launches)", "bound": "mfma",
-            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "ms_per_launch": ms, "flops_per_launch": flops, "launches": cls["plain"]["launches"],
-            "n_padded": (n + 127) // 128 * 128, "product_classes": classes}
+    tr = measured_traffic(mode) if n == 10000 else None
+    res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection launches)", "bound": "mfma",
+           "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": tr["traffic_bytes_per_launch"] if tr else None, "ms_per_launch": ms, "flops_per_launch": flops,
+           "launches": cls["plain"]["launches"], "n_padded": (n + 127) // 128 * 128, "product_classes": classes}
+    if tr:
+        res["traffic_detail"] = {"unit": "bytes per launch", "fetch": tr["fetch_bytes_per_launch"],
+                                 "write": tr["write_bytes_per_launch"],
+                                 "algorithmic": tr["algorithmic_bytes_per_launch"],
+                                 "source": "profiles/gemm_plain_n10000_traffic.md"}
+    return res
 
 
 def cpu_baseline(mode, n_sample):
@@ -238,6 +265,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device 3 times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X; this build has no multi-GPU path (--gpus must be 1).",
@@ -247,6 +276,18 @@ def main():
     import torch
     from paper_2507_09165_amd import inputs
     from paper_2507_09165_amd import psdproj as P
+
+    if args.copy_probe:
+        # a plain device copy of known size: the reference point that scales
+        # the FETCH_SIZE / WRITE_SIZE counters to bytes
+        a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}), flush=True)
+        return
 
     P.lib()
     dev = torch.device("cuda:0")
