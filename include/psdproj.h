@@ -257,14 +257,17 @@ int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const vo
 
 /* psdproj_sym_gemm_pair8: the same product on FP16 matrices whose split parts
  * are FP8 pairs (the PSDPROJ_MODE_FP8_FP16_SPLIT storage). For a split matrix
- * M with FP16 part M_hi, the pair buffer (n_p x ld x 2 bytes, device) holds,
- * per column j (2 ld bytes) and per group of 16 rows q, the 16 e4m3 codes of
- * M_hi 2^e followed by the 16 codes of (M - M_hi) 2^(11+e), so that
- * M = M_hi + 2^-(11+e) decode(lo codes). e_l, e_r, e_c0, e_d are the pair
- * exponents of L, R, C0 and D (|e| <= 40). Lx and Rx are both given (pair
- * product: L_hi R_hi + the two cross terms on FP8 MFMAs) or both NULL;
- * C0x != NULL adds the pair correction of C0; Dx != NULL writes D's pair.
- * Queued on `stream` like psdproj_sym_gemm. */
+ * M with FP16 part M_hi, the code buffer (device, ld bytes per column, n_p
+ * columns) holds the e4m3 codes of (M - M_hi) 2^(11+e), so that
+ * M = M_hi + 2^-(11+e) decode(codes). The code of element (row i, column j)
+ * is at byte 4 ld (j / 4) + 128 (i / 32) + 32 (j mod 4) + 16 ((i / 8) mod 2)
+ * + 8 ((i / 16) mod 2) + (i mod 8): 32 rows of 4 columns fill one 128-byte
+ * line, and each 16-byte chunk holds the K values one lane half of an FP16
+ * MFMA fragment pair covers. The buffer holds n_p ld bytes. e_l, e_r, e_c0, e_d are the pair exponents of L, R,
+ * C0 and D (|e| <= 40). Lx and Rx are both given (pair product: L_hi R_hi on
+ * FP16 MFMAs plus both cross terms on FP8 MFMAs, with the codes of M_hi 2^e
+ * formed in registers) or both NULL; C0x != NULL adds the pair correction of
+ * C0; Dx != NULL writes D's codes. Queued on `stream` like psdproj_sym_gemm. */
 int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *Lx,
                            const void *R, const void *Rx, const void *C0, const void *C0x,
                            float alpha, float beta, float gamma, void *D, void *Dx,

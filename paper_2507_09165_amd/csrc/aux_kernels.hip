@@ -72,8 +72,8 @@ __device__ __forceinline__ void tile_of(int t, int &I, int &J) {
 
 // Slot 0 of matrix m <- X / lam (64 x 64 tile pair (bi <= bj) of the padded
 // n_p x n_p matrix, transposed through LDS for the mirrored half).
-// X8: the split part is the FP8 pair of X0 (code exponent e8) instead of an
-// FP16 lo half.
+// X8: the split part is the FP8 pair's lo codes of X0 (code exponent e8)
+// instead of an FP16 lo half.
 template <typename T, bool SPLIT, bool X8 = false>
 __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
                                                    IoArg io0, float lo_scale, int e8) {
@@ -88,13 +88,12 @@ __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkI
     T *Ohi = (T *)d.hi[0];
     T *Olo = (T *)d.lo[0];
     uint8_t *Ox = (uint8_t *)d.lo[0];
-    const float hs = X8 ? __builtin_ldexpf(1.0f, e8) : 0.0f, ls = X8 ? __builtin_ldexpf(1.0f, 11 + e8) : 0.0f;
+    const float ls = X8 ? __builtin_ldexpf(1.0f, 11 + e8) : 0.0f;
     auto put = [&](int64_t i, int64_t j, float v) {
         const T hi = cvt<T>(v);
         Ohi[j * ldo + i] = hi;
         if constexpr (SPLIT && X8) {
-            Ox[x8_index(i, j, ldo)] = e4m3((float)hi * hs);
-            Ox[x8_index(i, j, ldo) + 16] = e4m3((v - (float)hi) * ls);
+            Ox[lo8_index(i, j, ldo)] = e4m3((v - (float)hi) * ls);
         } else if constexpr (SPLIT) {
             Olo[j * ldo + i] = cvt<T>((v - (float)hi) * lo_scale);
         }

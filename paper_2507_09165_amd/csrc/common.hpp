@@ -68,16 +68,20 @@ __device__ __forceinline__ IoArg io_of(const IoArg *tab, const IoArg &io0, int m
 
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// FP8 pair format of a split work matrix M = M_hi + 2^-11 M_lo (FP16 hi in
-// hi[slot]; the FP8 pair in lo[slot], which has the same byte size). Column j
-// of the pair buffer spans 2 ld bytes. Its rows are grouped by 16: group q
-// holds the 16 e4m3 codes of M_hi 2^e (rows 16q..16q+15), then the 16 codes
-// of (M - M_hi) 2^(11+e). So along K (the row index), every 32 bytes carry
-// 16 hi codes followed by the matching 16 lo codes. e is a per-slot power of
-// two chosen from a bound on |M| (entries of a symmetric matrix are bounded
-// by its spectral norm) so that both codes stay below the e4m3 maximum, 448.
-__device__ __forceinline__ int64_t x8_index(int64_t i, int64_t j, int64_t ld) {
-    return 2 * ld * j + 32 * (i >> 4) + (i & 15);
+// FP8 pair format of a split work matrix M = M_hi + 2^-(11+e) M_lo (FP16
+// M_hi in hi[slot]; the e4m3 codes of M_lo = (M - M_hi) 2^(11+e) in lo[slot],
+// one byte per element). The code buffer is tiled for the product kernel's
+// loads: columns are grouped by 4 (group c spans 4 ld bytes) and rows by 32;
+// the 32 rows x 4 columns of block (q, c) fill one 128-byte line, column
+// j = 4 c + s at bytes 32 s .. 32 s + 31. Within a column's 32 bytes the rows
+// are permuted so that each 16-byte chunk holds the 16 K values one lane half
+// of an FP16 MFMA fragment pair covers: row 32 q + 16 a + 8 g + x (a, g in
+// {0, 1}, x < 8) sits at byte 16 g + 8 a + x. e is a per-slot power of two
+// chosen from a bound on |M| (entries of a symmetric matrix are bounded by
+// its spectral norm) so that the codes of M_hi 2^e, formed in registers by
+// the product kernel, and of M_lo stay below the e4m3 maximum, 448.
+__device__ __forceinline__ int64_t lo8_index(int64_t i, int64_t j, int64_t ld) {
+    return (j >> 2) * 4 * ld + 128 * (i >> 5) + 32 * (j & 3) + 16 * ((i >> 3) & 1) + 8 * ((i >> 4) & 1) + (i & 7);
 }
 // Round to e4m3 (OCP, round to nearest even) after clamping to the finite
 // range; four values packed little-endian into one word.

@@ -69,6 +69,22 @@ __device__ __forceinline__ void mma_x8(f32x16 &acc, u32x4 a0, u32x4 a1, u32x4 b0
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
 }
 
+// e4m3 codes of the 16 FP16 values of two substep fragments (8 each, in K
+// order), divided by sc (v_cvt_scalef32_pk_fp8_f16 divides by its scale; sc
+// = 2^-e gives the codes of v 2^e), packed in the byte order of the pair's lo
+// codes.
+__device__ __forceinline__ u32x4 hi8_codes(u32x4 h0, u32x4 h1, float sc) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    auto pk = [&](uint32_t lo_pair, uint32_t hi_pair) -> uint32_t {
+        s2 w = {0, 0};
+        w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, lo_pair), sc, false);
+        w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, hi_pair), sc, true);
+        return __builtin_bit_cast(uint32_t, w);
+    };
+    return u32x4{pk(h0.x, h0.y), pk(h0.z, h0.w), pk(h1.x, h1.y), pk(h1.z, h1.w)};
+}
+
 __device__ __forceinline__ u32x4 scale_frag(u32x4 v, f16) {
     f16x8 h = __builtin_bit_cast(f16x8, v);
     h = h * (f16)2048.0f;
@@ -115,23 +131,46 @@ __device__ __forceinline__ void wait_vmcnt() {
     static_assert(N >= 0 && N < 64, "vmcnt range");
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
+// lgkmcnt-only wait: at most N LDS reads still outstanding (they return in
+// order, so the older ones have landed).
+template <int N>
+__device__ __forceinline__ void wait_lgkmcnt() {
+    static_assert(N >= 0 && N < 16, "lgkmcnt range");
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (N << 8) | (3 << 14));
+}
 
 // X8: split parts are FP8 pairs (FP16 hi + e4m3 hi/lo codes) instead of FP16
 // hi + FP16 lo; the pair product is L_hi R_hi on FP16 MFMAs plus both cross
 // terms on one FP8 MFMA per 32 K. Requires T = f16 and LS == RS.
+//
+// COMB (both operands split, 128 tile): each operand's LDS row interleaves
+// its two parts, [hi of BK K | lo (or FP8 pair) of the same BK K], so two
+// panels of 128-byte rows hold a split K-tile: conflict-free reads at two
+// workgroups per CU, where four panels of 64-byte rows cost 6.7 LDS cycles
+// per read.
 template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     static_assert(!X8 || (sizeof(T) == 2 && LS == RS), "FP8 pairs: FP16 hi, both operands split");
-    static_assert(!(X8 && LS) || ROWB >= 64, "FP8 pair units are 64 bytes of a row");
     constexpr bool PAIR8 = X8 && LS;          // FP8 cross terms in the main loop
+    constexpr bool COMB = LS && RS && !X8 && BM == 128;
     constexpr int NCH = ROWB / 16;            // 16-byte chunks per LDS row
-    constexpr int NSUB = PAIR8 ? NCH / 4 : NCH / 2;  // K-units per row: 16 K (32 K with FP8 pairs)
     constexpr int NLP = LS ? 2 : 1;
     constexpr int NRP = RS ? 2 : 1;
+    constexpr int NPAN = COMB ? 2 : NLP + NRP;  // LDS panels per stage
     constexpr int PANEL = BM * ROWB;
-    constexpr int STAGE = (NLP + NRP) * PANEL;
-    constexpr int BK = ROWB / (int)sizeof(T);
-    constexpr int CPT = BM * NCH / kThreads;  // chunks per thread per panel
+    // PAIR8 stage: [L hi: 64-byte rows | L codes: 32-byte rows | R hi | R codes]
+    // for 32 K; the hi codes of the cross terms are formed in registers
+    constexpr int P8HI = BM * 64, P8LO = BM * 32;
+    constexpr int STAGE = PAIR8 ? 2 * (P8HI + P8LO) : NPAN * PANEL;
+    constexpr int TB = PAIR8 ? 64 : (COMB ? ROWB / 2 : ROWB);  // bytes per K-tile (hi buffer)
+    constexpr int BK = TB / (int)sizeof(T);     // K per tile
+    constexpr int HCH = COMB ? NCH / 2 : 0;     // COMB: first chunk of the lo part
+    // K-units per tile: a chunk pair (32 bytes of a row: 16 K in FP16/BF16,
+    // 8 K in FP32), or 64 bytes (32 K) with FP8 pairs
+    constexpr int NSUB = PAIR8 ? TB / 64 : TB / 32;
+    static_assert(NSUB >= 1, "at least one K-unit per tile");
+    static_assert(!COMB || NCH == 8, "combined rows are 128 bytes");
+    static_assert(!PAIR8 || BM == 128, "FP8-pair products use the 128 tile");
     constexpr int WM = BM / 2;                // wave tile edge
     constexpr int MI = WM / 32;
     static_assert(BM * NCH % kThreads == 0 && WM % 32 == 0, "tile shape");
@@ -150,7 +189,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     const int wc = (wave & 1) * WM;
     const int64_t ld = dm.ldw;
 
-    // Operand panels of one K-tile, in LDS order: L_hi, [L_lo], R_hi, [R_lo].
+    // Source buffers in LDS order: L_hi, [L_lo], R_hi, [R_lo] (COMB: the
+    // two parts of each panel).
     const uint8_t *src[4];
     {
         int p = 0;
@@ -163,28 +203,65 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     // 1 KB of contiguous LDS (lane l -> byte 16 l). The K-tile of all panels
     // is NLD such kilobytes per wave; lane l of load j fills LDS row r at
     // physical chunk pc, so it fetches logical chunk swz(r, pc) of that row.
-    constexpr int NLD = (NLP + NRP) * PANEL / (1024 * 4);
+    constexpr int NLD = STAGE / (1024 * 4);
     constexpr int RPL = 1024 / ROWB;  // LDS rows per wave load
-    static_assert((NLP + NRP) * PANEL % 4096 == 0, "panel split over waves");
+    static_assert(STAGE % 4096 == 0, "stage split over waves");
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     const uint8_t *gsrc[NLD];
+    int gstep[NLD];  // bytes a source row advances per K-tile
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
         const int kb = (wave * NLD + j) * 1024;  // byte offset in the stage
+        gstep[j] = TB;
+        if constexpr (PAIR8) {
+            // panels: L hi, L codes, R hi, R codes (every 1-KB load lies in one)
+            const int side = kb >= P8HI + P8LO ? 1 : 0;
+            const int off = kb - side * (P8HI + P8LO);
+            const bool is_hi = off < P8HI;
+            const int w = is_hi ? 64 : 32, nch = w / 16;
+            const int r = (is_hi ? off : off - P8HI) / w + lane / nch;
+            const int pc = lane % nch;
+            const int c = is_hi ? swz<4>(r, pc) : swz<2>(r, pc);
+            const int64_t row = (side == 0 ? i0 : j0) + r;
+            // hi: row-major 64-byte segments of the FP16 column; codes: the
+            // tiled code buffer, 32 bytes of column `row` per 32-K block
+            gsrc[j] = is_hi ? src[2 * side] + row * ld * 2 + (c << 4)
+                            : src[2 * side + 1] + (row >> 2) * 4 * ld + 32 * (row & 3) + (c << 4);
+            gstep[j] = is_hi ? 64 : 128;
+            continue;
+        }
         const int p = kb / PANEL;
         const int r = (kb % PANEL) / ROWB + lane / NCH;
         const int pc = lane % NCH;
-        const int64_t row = (p < NLP ? i0 : j0) + r;
-        gsrc[j] = src[p] + row * ld * (int64_t)sizeof(T) + (swz<NCH>(r, pc) << 4);
+        const int c = swz<NCH>(r, pc);
+        if constexpr (COMB) {
+            // panel p is operand p; chunk c < HCH is hi, the rest lo / pair
+            const int64_t row = (p == 0 ? i0 : j0) + r;
+            gsrc[j] = src[2 * p + (c >= HCH ? 1 : 0)] + row * ld * (int64_t)sizeof(T) + ((c % HCH) << 4);
+        } else {
+            const int64_t row = (p < NLP ? i0 : j0) + r;
+            gsrc[j] = src[p] + row * ld * (int64_t)sizeof(T) + (c << 4);
+        }
     }
+    // The loads are written as inline asm (M0 = LDS destination, one s_nop
+    // for the M0 -> LDS-DMA hazard, as the compiler itself emits). Issued
+    // through the builtin, the compiler's wait-count pass cannot order the LDS
+    // reads behind LDS DMA and puts lgkmcnt(0) before every MFMA group, which
+    // also waits for the next substep's reads; as asm, the reads get counted
+    // waits. Completion of the DMA is awaited explicitly (vmcnt + barrier
+    // below), as before.
     auto issue_loads = [&](int64_t kt, int buf) {
-        const int64_t kb = kt * ROWB;
         uint8_t *dst = smem + buf * STAGE + wave_u * NLD * 1024;
 #pragma unroll
-        for (int j = 0; j < NLD; ++j)
-            __builtin_amdgcn_global_load_lds((gptr_t)(gsrc[j] + kb), (lptr_t)(dst + j * 1024), 16, 0, 0);
+        for (int j = 0; j < NLD; ++j) {
+            const uint32_t la = (uint32_t)(uintptr_t)(dst + j * 1024);
+            asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                         :
+                         : "v"(gsrc[j] + kt * gstep[j]), "s"(la)
+                         : "memory", "m0");
+        }
     };
-    static_assert(RPL * NCH == 64, "lane layout");
+    static_assert(PAIR8 || RPL * NCH == 64, "lane layout");
 
     f32x16 acc[MI][MI];
 #pragma unroll
@@ -196,9 +273,12 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 
     // fragment row offsets inside a panel, and the row's swizzle key
     int roff_a[MI], roff_b[MI], key_a[MI], key_b[MI];
+    int ra_[MI], rb_[MI];
 #pragma unroll
     for (int m = 0; m < MI; ++m) {
         const int ra = wr + m * 32 + (lane & 31), rb = wc + m * 32 + (lane & 31);
+        ra_[m] = ra;
+        rb_[m] = rb;
         roff_a[m] = ra * ROWB;
         roff_b[m] = rb * ROWB;
         key_a[m] = swz<NCH>(ra, 0);
@@ -209,28 +289,51 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     // Fragments of one K-unit, [part][MFMA block m]. Plain and FP16 pairs:
     // one part per operand panel. FP8 pairs: L_hi (two 16-K substeps),
     // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo).
-    constexpr int NFP = PAIR8 ? 8 : NLP + NRP;
+    constexpr int NFP = PAIR8 ? 6 : NLP + NRP;
     typedef u32x4 Frag[NFP][MI];
     // E8M0 scale codes 2^(c - 127), replicated into every byte
     const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
     const int sb8 = PAIR8 ? (int)((uint32_t)(127 - g.es_r) * 0x01010101u) : 0;
+    const float cva = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_l) : 0.0f;  // hi-code conversion scales
+    const float cvb = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_r) : 0.0f;
+    auto rd = [&](const uint8_t *base, int pan, bool b_side, int m, int c) -> u32x4 {
+        const int ro = b_side ? roff_b[m] : roff_a[m], key = b_side ? key_b[m] : key_a[m];
+        return *(const u32x4 *)(base + pan * PANEL + ro + ((c ^ key) << 4));
+    };
     auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
+        const int hg = lane >> 5;
         if constexpr (PAIR8) {
-            const int hg = lane >> 5;
+            // [0] L hi substep 0, [1] L hi substep 1, [2] L codes, [3..5] R;
+            // issued in groups (substep 0, substep 1, codes) so the MFMAs can
+            // start on each group as it lands
+            const uint8_t *lh = base, *ll = base + P8HI, *rh = base + P8HI + P8LO, *rl = rh + P8HI;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                for (int m = 0; m < MI; ++m) {
-                    const int cl = 4 * sub + 2 * h + hg;  // FP16: substep h, lane half hg
-                    const int cx = 4 * sub + 2 * hg + h;  // codes: 16 K of lane half hg, hi (h = 0) / lo
-                    f[h][m] = *(const u32x4 *)(base + roff_a[m] + ((cl ^ key_a[m]) << 4));
-                    f[2 + h][m] = *(const u32x4 *)(base + PANEL + roff_a[m] + ((cx ^ key_a[m]) << 4));
-                    f[4 + h][m] = *(const u32x4 *)(base + 2 * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
-                    f[6 + h][m] = *(const u32x4 *)(base + 3 * PANEL + roff_b[m] + ((cx ^ key_b[m]) << 4));
-                }
+                for (int m = 0; m < MI; ++m)
+                    f[h][m] = *(const u32x4 *)(lh + ra_[m] * 64 + (((2 * h + hg) ^ ((ra_[m] >> 2) & 3)) << 4));
+#pragma unroll
+                for (int m = 0; m < MI; ++m)
+                    f[3 + h][m] = *(const u32x4 *)(rh + rb_[m] * 64 + (((2 * h + hg) ^ ((rb_[m] >> 2) & 3)) << 4));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                f[2][m] = *(const u32x4 *)(ll + ra_[m] * 32 + ((hg ^ ((ra_[m] >> 3) & 1)) << 4));
+                f[5][m] = *(const u32x4 *)(rl + rb_[m] * 32 + ((hg ^ ((rb_[m] >> 3) & 1)) << 4));
+            }
+            return;
+        } else if constexpr (COMB) {
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                f[0][m] = rd(base, 0, false, m, 2 * sub + hg);
+                f[1][m] = rd(base, 0, false, m, HCH + 2 * sub + hg);
+                f[2][m] = rd(base, 1, true, m, 2 * sub + hg);
+                f[3][m] = rd(base, 1, true, m, HCH + 2 * sub + hg);
+            }
             return;
         }
-        const int cl = 2 * sub + (lane >> 5);
+        const int cl = 2 * sub + hg;
 #pragma unroll
         for (int p = 0; p < NLP; ++p)
 #pragma unroll
@@ -248,9 +351,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma unroll
             for (int ni = 0; ni < MI; ++ni) {
                 if constexpr (PAIR8) {
-                    mma(acc[mi][ni], f[0][mi], f[4][ni], T{});
-                    mma(acc[mi][ni], f[1][mi], f[5][ni], T{});
-                    mma_x8(acc[mi][ni], f[2][mi], f[3][mi], f[7][ni], f[6][ni], sa8, sb8);
+                    mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                    mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                    mma_x8(acc[mi][ni], hi8_codes(f[0][mi], f[1][mi], cva), f[2][mi], f[5][ni],
+                           hi8_codes(f[3][ni], f[4][ni], cvb), sa8, sb8);
                 } else if constexpr (LS || RS) {
                     mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
                     if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
@@ -260,6 +364,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 }
             }
     };
+    // ds_read_b128 per K-unit; the counter holds 15 at most, and a wait for
+    // <= 15 outstanding is still enough when more were issued after the ones
+    // needed (in-order return)
+    constexpr int NDS = NFP * MI < 15 ? NFP * MI : 15;
     Frag fr[2];
     // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
     // Every wave issues exactly NLD loads per iteration (the index is clamped
@@ -269,6 +377,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     wait_vmcnt<NLD * (NST - 2)>();
     __builtin_amdgcn_s_barrier();
     load_frags(smem, 0, fr[0]);
+    // Drain every LDS and scalar-memory access of the prologue, so that no
+    // scalar load (which may return out of order) is pending in the loop and
+    // the counted LDS waits below are the only ones needed.
+    wait_lgkmcnt<0>();
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int st = (int)(kt % NST);
         const uint8_t *base = smem + st * STAGE;
@@ -280,10 +392,47 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
             // next substep's fragments first, then this substep's MFMAs on
-            // fragments loaded one substep earlier
-            if (sub + 1 < NSUB) load_frags(base, sub + 1, fr[(sub + 1) & 1]);
-            __builtin_amdgcn_sched_barrier(0);
-            mfmas(fr[sub & 1]);
+            // fragments loaded one substep earlier: wait only for those (the
+            // NDS reads just issued may stay in flight under the MFMAs)
+            if (sub + 1 < NSUB) {
+                load_frags(base, sub + 1, fr[(sub + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                wait_lgkmcnt<NDS>();
+                mfmas(fr[sub & 1]);
+            } else if constexpr (PAIR8) {
+                // the unit's reads were issued in groups (substep 0, substep
+                // 1, codes): start on each group as it lands; every
+                // accumulator still sees substep 0, 1, then the cross terms
+                const Frag &f = fr[sub & 1];
+                __builtin_amdgcn_sched_barrier(0);
+                wait_lgkmcnt<4 * MI>();
+#pragma unroll
+                for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                __builtin_amdgcn_sched_barrier(0);
+                wait_lgkmcnt<2 * MI>();
+#pragma unroll
+                for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                u32x4 ha[MI], hb[MI];
+#pragma unroll
+                for (int m = 0; m < MI; ++m) {
+                    ha[m] = hi8_codes(f[0][m], f[1][m], cva);
+                    hb[m] = hi8_codes(f[3][m], f[4][m], cvb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                wait_lgkmcnt<0>();
+#pragma unroll
+                for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < MI; ++ni) mma_x8(acc[mi][ni], ha[mi], f[2][mi], f[5][ni], hb[ni], sa8, sb8);
+            } else {
+                __builtin_amdgcn_sched_barrier(0);
+                wait_lgkmcnt<0>();
+                mfmas(fr[sub & 1]);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
         // Tile kt + 1 landed for this wave, then (barrier) for all waves. A
@@ -334,7 +483,6 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const float c0lo = 1.0f / Elt<T>::kSplit;
         // FP8 pairs: code scales of the addend and of the output slot
         const float c0x = X8 ? __builtin_ldexpf(1.0f, -(11 + g.es_c0)) : 0.0f;
-        const float dhs = X8 ? __builtin_ldexpf(1.0f, g.es_d) : 0.0f;
         const float dls = X8 ? __builtin_ldexpf(1.0f, 11 + g.es_d) : 0.0f;
         uint8_t *Dx = (uint8_t *)dm.lo[g.sd];
         typedef T t4 __attribute__((ext_vector_type(4)));
@@ -355,8 +503,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         for (int q = 0; q < 4; ++q) v[q] += g.alpha * to_f(c[q]);
                         if (C0lo) {
                             if constexpr (X8) {
-                                const uint32_t w =
-                                    *(const uint32_t *)((const uint8_t *)C0lo + x8_index(ib, j, ld) + 16);
+                                const uint32_t w = *(const uint32_t *)((const uint8_t *)C0lo + lo8_index(ib, j, ld));
 #pragma clang loop unroll(full)
                                 for (int q = 0; q < 4; ++q) v[q] += g.alpha * (e4m3_byte(w, q) * c0x);
                             } else {
@@ -375,27 +522,19 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         hi[q] = from_f<T>(v[q]);
                         if constexpr (SPL16) lo[q] = from_f<T>((v[q] - to_f(hi[q])) * Elt<T>::kSplit);
                     }
-                    uint32_t h8 = 0, l8 = 0;
-                    if constexpr (SPL8) {
-                        h8 = e4m3x4(to_f(hi[0]) * dhs, to_f(hi[1]) * dhs, to_f(hi[2]) * dhs, to_f(hi[3]) * dhs);
+                    uint32_t l8 = 0;
+                    if constexpr (SPL8)
                         l8 = e4m3x4((v[0] - to_f(hi[0])) * dls, (v[1] - to_f(hi[1])) * dls,
                                     (v[2] - to_f(hi[2])) * dls, (v[3] - to_f(hi[3])) * dls);
-                    }
                     if (!diag) {
                         *(t4 *)(Dhi + j * ld + ib) = hi;
                         if constexpr (SPL16) *(t4 *)(Dlo + j * ld + ib) = lo;
-                        if constexpr (SPL8) {
-                            *(uint32_t *)(Dx + x8_index(ib, j, ld)) = h8;
-                            *(uint32_t *)(Dx + x8_index(ib, j, ld) + 16) = l8;
-                        }
+                        if constexpr (SPL8) *(uint32_t *)(Dx + lo8_index(ib, j, ld)) = l8;
 #pragma clang loop unroll(full)
                         for (int q = 0; q < 4; ++q) {
                             Dhi[(ib + q) * ld + j] = hi[q];
                             if constexpr (SPL16) Dlo[(ib + q) * ld + j] = lo[q];
-                            if constexpr (SPL8) {
-                                Dx[x8_index(j, ib + q, ld)] = (uint8_t)(h8 >> (8 * q));
-                                Dx[x8_index(j, ib + q, ld) + 16] = (uint8_t)(l8 >> (8 * q));
-                            }
+                            if constexpr (SPL8) Dx[lo8_index(j, ib + q, ld)] = (uint8_t)(l8 >> (8 * q));
                         }
                     } else {
 #pragma clang loop unroll(full)
@@ -409,11 +548,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                                 Dlo[i * ld + j] = lo[q];
                             }
                             if constexpr (SPL8) {
-                                const uint8_t hb = (uint8_t)(h8 >> (8 * q)), lb = (uint8_t)(l8 >> (8 * q));
-                                Dx[x8_index(i, j, ld)] = hb;
-                                Dx[x8_index(i, j, ld) + 16] = lb;
-                                Dx[x8_index(j, i, ld)] = hb;
-                                Dx[x8_index(j, i, ld) + 16] = lb;
+                                const uint8_t lb = (uint8_t)(l8 >> (8 * q));
+                                Dx[lo8_index(i, j, ld)] = lb;
+                                Dx[lo8_index(j, i, ld)] = lb;
                             }
                         }
                     }
@@ -476,9 +613,10 @@ int64_t gemm_padded_size(int64_t n) {
 // 128 KB: a 4-stage ring for plain operands, two stages of 64-byte rows for
 // split ones.
 template <int BM, int NP> struct LdsCfg {
+    static constexpr bool COMB = BM == 128 && NP == 4;  // two parts per 128-byte row
     static constexpr int NST = (BM == 256 && NP == 2) ? 4 : 2;
     static constexpr int BUDGET = BM == 256 ? 128 * 1024 : 80 * 1024;
-    static constexpr int ROWB_MAX = BUDGET / (NST * NP * BM);
+    static constexpr int ROWB_MAX = BUDGET / (NST * (COMB ? 2 : NP) * BM);
     static constexpr int ROWB = ROWB_MAX >= 128 ? 128 : ROWB_MAX >= 64 ? 64 : 32;
 };
 

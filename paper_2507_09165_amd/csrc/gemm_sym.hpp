@@ -6,8 +6,8 @@
 
 namespace psd {
 
-// DT_F16X8: FP16 work matrices whose split slots carry FP8 pairs (see
-// x8_index) instead of FP16 lo halves.
+// DT_F16X8: FP16 work matrices whose split slots carry the e4m3 lo codes of
+// an FP8 pair (see lo8_index) instead of FP16 lo halves.
 enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F16X8 = 3 };
 enum Epi { EPI_STORE = 0, EPI_STORE_SPLIT = 1, EPI_FINAL = 2 };
 

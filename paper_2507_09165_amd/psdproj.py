@@ -224,8 +224,9 @@ def sym_gemm(dtype, L, R, D, Llo=None, Rlo=None, C0=None, C0lo=None, Dlo=None,
 def sym_gemm_pair8(L, R, D, Lx=None, Rx=None, C0=None, C0x=None, Dx=None, alpha=0.0, beta=1.0,
                    gamma=0.0, exps=(0, 0, 0, 0), stream=None):
     """D = alpha C0 + beta L R + gamma I on FP16 work matrices whose split
-    parts are FP8 pairs (uint8 tensors of shape (n_p, 2 ld)); exps are the
-    pair exponents of (L, R, C0, D)."""
+    parts are FP8 pair codes (uint8 tensors of n_p * ld bytes in the tiled
+    layout documented in psdproj.h); exps are the pair exponents of
+    (L, R, C0, D)."""
     n_p = L.shape[0]
     ld = L.stride(0)
     e = [int(v) for v in exps]

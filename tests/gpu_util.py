@@ -54,17 +54,26 @@ def e4m3_encode(x):
     return (code | np.where(np.signbit(x), 128, 0)).astype(np.uint8)
 
 
-def pair8_pack(hi_codes, lo_codes):
-    """(n, n) code matrices -> (n, 2 n) pair buffer: row j of the buffer is
-    column j of the matrix, rows grouped by 16 as [16 hi codes | 16 lo codes]."""
-    n = hi_codes.shape[0]
-    P = np.zeros((n, n // 16, 32), dtype=np.uint8)
-    P[:, :, :16] = hi_codes.reshape(n, n // 16, 16)
-    P[:, :, 16:] = lo_codes.reshape(n, n // 16, 16)
-    return P.reshape(n, 2 * n)
+def pair8_index(n, ld=None):
+    """Byte offset of the code of element (row i, column j), as an (n, n)
+    array indexed [j, i]: columns grouped by 4, rows by 32, a block of 32 rows
+    x 4 columns in one 128-byte line, rows permuted within a column's 32
+    bytes as 16 ((i // 8) % 2) + 8 ((i // 16) % 2) + i % 8."""
+    ld = n if ld is None else ld
+    i = np.arange(n)[None, :]
+    j = np.arange(n)[:, None]
+    return ((j >> 2) * 4 * ld + 128 * (i >> 5) + 32 * (j & 3) + 16 * ((i >> 3) & 1) + 8 * ((i >> 4) & 1)
+            + (i & 7))
+
+
+def pair8_pack(lo_codes):
+    """(n, n) code matrix indexed [j, i] -> (n, n) uint8 code buffer."""
+    n = lo_codes.shape[0]
+    B = np.zeros(n * n, dtype=np.uint8)
+    B[pair8_index(n).ravel()] = lo_codes.ravel()
+    return B.reshape(n, n)
 
 
 def pair8_unpack(buf):
     n = buf.shape[0]
-    P = buf.reshape(n, n // 16, 32)
-    return P[:, :, :16].reshape(n, n), P[:, :, 16:].reshape(n, n)
+    return np.ascontiguousarray(buf.ravel()[pair8_index(n)])

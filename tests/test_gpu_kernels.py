@@ -141,26 +141,24 @@ def test_sym_gemm_tile_shapes_agree(dt, split):
 
 
 def _pair8(M, e):
-    """FP16 hi and the FP8 pair of a symmetric FP64 matrix; returns the device
-    tensors and the value the pair represents."""
+    """FP16 hi and the FP8 pair codes of a symmetric FP64 matrix; returns the
+    device tensors and the value the pair represents."""
     from gpu_util import e4m3_encode, e4m3_values, pair8_pack
-    import torch
     hi = M.astype(np.float16)
     hi64 = hi.astype(np.float64)
-    hc = e4m3_encode(hi64 * 2.0 ** e)
     lc = e4m3_encode((M - hi64) * 2.0 ** (11 + e))
     val = hi64 + e4m3_values()[lc] * 2.0 ** -(11 + e)
-    return to_dev(hi), to_dev(pair8_pack(hc, lc)), val
+    return to_dev(hi), to_dev(pair8_pack(lc)), val
 
 
 @pytest.mark.parametrize("n_p", [256, 384])
 def test_sym_gemm_pair8(n_p):
-    """FP8-pair product: L_hi R_hi + both cross terms on the e4m3 MFMA, the
-    pair addend and the pair output. Checked against the FP64 product of the
-    values the pairs represent, and the output codes bit for bit against the
-    e4m3 rounding of the stored FP16 part."""
+    """FP8-pair product: L_hi R_hi on FP16 MFMAs, both cross terms on the e4m3
+    MFMA (the codes of M_hi 2^e formed in registers), the pair addend and the
+    pair output. Checked against the FP64 product of the values the pairs
+    represent; the output codes are symmetric."""
     import torch
-    from gpu_util import e4m3_encode, e4m3_values, pair8_unpack
+    from gpu_util import e4m3_values, pair8_unpack
     say("sym_gemm pair8", n_p)
     A = inputs.goe(n_p, 71, np.float64)
     Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)          # entries up to ~2.5
@@ -171,25 +169,22 @@ def test_sym_gemm_pair8(n_p):
     Rh, Rx, Rv = _pair8(Bm, eR)
     Ch, Cx, Cv = _pair8(A, eC)
     D = torch.zeros_like(Lh)
-    Dx = torch.zeros(n_p, 2 * n_p, dtype=torch.uint8, device=dev())
+    Dx = torch.zeros(n_p, n_p, dtype=torch.uint8, device=dev())
     P.sym_gemm_pair8(Lh, Rh, D, Lx=Lx, Rx=Rx, C0=Ch, C0x=Cx, Dx=Dx, alpha=0.5, beta=-1.25,
                      exps=(eL, eR, eC, eD))
     torch.cuda.synchronize()
     Dhi = D.cpu().numpy().astype(np.float64)
-    hc, lc = pair8_unpack(Dx.cpu().numpy())
+    lc = pair8_unpack(Dx.cpu().numpy())
     got = Dhi + e4m3_values()[lc] * 2.0 ** -(11 + eD)
     ref = 0.5 * Cv + -1.25 * (Lv @ Rv)
     err = rel_fro(got, ref)
-    plain = rel_fro((0.5 * A.astype(np.float16).astype(np.float64)
-                     - 1.25 * (A.astype(np.float16).astype(np.float64) @ Bm.astype(np.float16).astype(np.float64))
-                     ).astype(np.float16), ref)
+    A16, B16 = A.astype(np.float16).astype(np.float64), Bm.astype(np.float16).astype(np.float64)
+    plain = rel_fro((0.5 * A16 - 1.25 * (A16 @ B16)).astype(np.float16), ref)
     say("  pair8 rel err", err, "plain fp16", plain)
     assert err < 1.5e-4 and err < plain / 4, (err, plain)
     np.testing.assert_array_equal(Dhi, Dhi.T)
-    np.testing.assert_array_equal(hc, hc.T)
-    np.testing.assert_array_equal(lc, lc.T)
     tab = e4m3_values()  # compare decoded codes: -0 and +0 are one value
-    np.testing.assert_array_equal(tab[hc], tab[e4m3_encode(Dhi * 2.0 ** eD)])
+    np.testing.assert_array_equal(tab[lc], tab[lc.T])
 
 
 def test_sym_gemm_pair8_plain_operands_pair_output():
@@ -204,11 +199,11 @@ def test_sym_gemm_pair8_plain_operands_pair_output():
     Ch, Cx, Cv = _pair8(A, 7)
     L = to_dev(Ah.astype(np.float16))
     D = torch.zeros_like(L)
-    Dx = torch.zeros(n_p, 2 * n_p, dtype=torch.uint8, device=dev())
+    Dx = torch.zeros(n_p, n_p, dtype=torch.uint8, device=dev())
     # ||D|| <= 2 * 2 + 0.75 * 4 = 7: pair exponent 5 keeps codes below 448
     P.sym_gemm_pair8(L, L, D, C0=Ch, C0x=Cx, Dx=Dx, alpha=2.0, beta=0.75, exps=(0, 0, 7, 5))
     torch.cuda.synchronize()
-    hc, lc = pair8_unpack(Dx.cpu().numpy())
+    lc = pair8_unpack(Dx.cpu().numpy())
     got = D.cpu().numpy().astype(np.float64) + e4m3_values()[lc] * 2.0 ** -16
     ref = 2.0 * Cv + 0.75 * (Ah @ Ah)
     assert rel_fro(got, ref) < 5e-5, rel_fro(got, ref)
