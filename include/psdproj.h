@@ -143,11 +143,19 @@ int psdproj_release(void);
 
 const char *psdproj_status_string(int status);
 
-/* Tuning hook (process-wide, not thread-safe against concurrent launches):
- * "gemm_tile" = 0 (automatic), 128 or 256 forces the GEMM tile edge where it
- * divides the padded size; "gemm_block" = H * 256 + W sets the blocking of
- * the GEMM tile schedule (H tile rows x W tile columns per block).
- * Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
+/* Tuning hook (process-wide, not thread-safe against concurrent launches).
+ * By default plain products of matrices with n >= 6144 (FP16/BF16 modes) run
+ * their whole rounds of 256 x 256 tiles (one workgroup per CU) and the last
+ * partial round as 128 x 128 tiles; split products and smaller matrices run
+ * 128 tiles. Any tiling gives bitwise-identical results.
+ * "gemm_tile" = 0 (automatic), 128 (128 tiles only) or 256 (256 tiles for all
+ * plain products, no tail split); "gemm_big_min" = n from which plain products
+ * use 256 tiles; "gemm_tail_cus" = CU count the tail rule assumes (0: the
+ * device's); "work_ld_pad" = elements added to the leading dimension of work
+ * matrices whose padded order n_p >= 2048 is a multiple of 1024 (default 128;
+ * multiple of 64; synchronises the device); "gemm_block" = H * 256 + W sets the blocking of the GEMM tile
+ * schedule (H tile rows x W tile columns per block). Plans are rebuilt after a
+ * change. Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
 int psdproj_tune(const char *key, int64_t value);
 
 /* ---- serving: a continuous-batching request loop -------------------------

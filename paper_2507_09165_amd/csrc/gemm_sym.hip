@@ -565,6 +565,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 // ~32 tiles resident on one XCD at a time form a compact 2D block that shares
 // H + W operand panels in its L2 instead of one panel per tile.
 static int g_tile_override = 0;  // tuning hook: force a tile edge (0 = automatic)
+static int g_tile_gen = 0;       // bumped by every tuning change (plans key on it)
 static int g_block_h = 4, g_block_w = 4;
 static std::mutex g_cfg_mu;
 
@@ -592,15 +593,57 @@ int gemm_pick_tile(int64_t K, int dtype) {
     return 128;
 }
 
-// Padded order of the work matrices: a multiple of the tile the launcher will
-// pick for it (the override, else 128). Any choice
-// gives bitwise-identical results: every element accumulates its K products
-// in the same order whatever the tile shape, and padding only adds zeros.
-int64_t gemm_padded_size(int64_t n) {
-    const int64_t m = n > 0 ? n : 1;
+// Plain products of large FP16/BF16 matrices run on the 256 tile: it moves
+// half the operand bytes per flop of the 128 tile, and the products are bound
+// by moving operands into LDS. Matrices smaller than this stay on 128 tiles.
+// (Tuning hooks: the size threshold, and the CU count the tail rule uses.)
+static int64_t g_big_min = 6144;
+static int g_tail_cus = 0;  // 0: the device's CU count
+
+bool gemm_use_big(int64_t n, int dtype) {
     const int o = g_tile_override;
-    if (o) return round_up(m, o);
-    return round_up(m, kTile);
+    if (o == 128) return false;
+    if (o == 256) return true;
+    return dtype != DT_F32 && n >= g_big_min;
+}
+int gemm_tail_cus(int device_cus) { return g_tail_cus > 0 ? g_tail_cus : device_cus; }
+
+// Padded order of the work matrices: a multiple of 256 where the 256 tile is
+// used, else of 128 (or of the override). Any choice gives bitwise-identical
+// results: every element accumulates its K products in the same order
+// whatever the tile shape, and padding only adds zeros.
+int64_t gemm_padded_size(int64_t n, bool big) {
+    const int64_t m = n > 0 ? n : 1;
+    if (big) return round_up(m, 256);
+    const int o = g_tile_override;
+    return round_up(m, o ? o : kTile);
+}
+
+int gemm_tile_generation() { return g_tile_gen; }
+
+// The 256 tile runs one workgroup per CU, so a list of B such tiles takes
+// ceil(B / CUs) rounds and a partial last round idles most of the chip
+// (measured: ~1000 TFLOP/s just under a whole number of rounds, ~860 just
+// over). The last B mod CUs tiles therefore run as 128 tiles (two workgroups
+// per CU, a quarter of the work each) in the product's second launch.
+void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out) {
+    out.big.clear();
+    out.small_plain.clear();
+    out.small_all.clear();
+    for (size_t m = 0; m < np.size(); ++m) {
+        if (big[m]) append_tile_order(out.big, (uint32_t)m, (int)(np[m] / 256));
+        else append_tile_order(out.small_plain, (uint32_t)m, (int)(np[m] / 128));
+        append_tile_order(out.small_all, (uint32_t)m, (int)(np[m] / 128));
+    }
+    const size_t tail = (g_tile_override == 256 || cus <= 0) ? 0 : out.big.size() % (size_t)cus;
+    for (size_t k = out.big.size() - tail; k < out.big.size(); ++k) {
+        const WorkItem w = out.big[k];
+        const uint32_t bi = w.y & 0xFFFFu, bj = w.y >> 16;
+        for (uint32_t sj = 2 * bj; sj < 2 * bj + 2; ++sj)
+            for (uint32_t si = 2 * bi; si < 2 * bi + 2; ++si)
+                if (si <= sj) out.small_plain.push_back(WorkItem{w.x, si | (sj << 16)});
+    }
+    out.big.resize(out.big.size() - tail);
 }
 
 // LDS configuration per (tile, operand panels). The 128 tile keeps two
@@ -610,11 +653,12 @@ int64_t gemm_padded_size(int64_t n) {
 // workgroup per CU). Deeper rings measured slower at n = 10^4 for the plain
 // product (1.20 ms per product with this ring; 1.36-1.52 ms with 3-5 stages of
 // 64- or 128-byte rows at one or two workgroups per CU). The 256 tile uses
-// 128 KB: a 4-stage ring for plain operands, two stages of 64-byte rows for
-// split ones.
+// 128 KB: two stages of 128-byte rows for plain operands (faster than a
+// 4-stage ring of 64-byte rows: 1.27 vs 1.31 ms at n_p = 10240), two of
+// 64-byte rows for split ones.
 template <int BM, int NP> struct LdsCfg {
     static constexpr bool COMB = BM == 128 && NP == 4;  // two parts per 128-byte row
-    static constexpr int NST = (BM == 256 && NP == 2) ? 4 : 2;
+    static constexpr int NST = 2;
     static constexpr int BUDGET = BM == 256 ? 128 * 1024 : 80 * 1024;
     static constexpr int ROWB_MAX = BUDGET / (NST * (COMB ? 2 : NP) * BM);
     static constexpr int ROWB = ROWB_MAX >= 128 ? 128 : ROWB_MAX >= 64 ? 64 : 32;
@@ -633,9 +677,12 @@ static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s) {
 
 template <int EPI>
 static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s) {
-    if (bm != 128) return hipErrorInvalidValue;
-    return pair ? launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s)
-                : launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s);
+    if (pair) return bm == 128 ? launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s) : hipErrorInvalidValue;
+    switch (bm) {
+        case 256: return launch_bm<f16, false, false, EPI, 256, true>(g, ntiles, s);
+        case 128: return launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, bool LS, bool RS, int EPI>
@@ -686,11 +733,20 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool 
     return hipErrorInvalidValue;
 }
 
-void gemm_set_tile_override(int bm) { g_tile_override = bm; }
+void gemm_set_big_tiles(int64_t min_n, int tail_cus) {
+    g_big_min = min_n;
+    g_tail_cus = tail_cus;
+    ++g_tile_gen;
+}
+void gemm_set_tile_override(int bm) {
+    g_tile_override = bm;
+    ++g_tile_gen;
+}
 void gemm_set_block_shape(int h, int w) {
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     g_block_h = h;
     g_block_w = w;
+    ++g_tile_gen;
 }
 
 }  // namespace psd

@@ -36,10 +36,28 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool 
 // Append matrix m's upper tiles (T x T tile grid) in the blocked schedule order.
 void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T);
 
-// Tile edge the launcher uses for a padded size K and dtype, and the padded
-// size used for a logical size n (a multiple of the tile it will run with).
+// Tile edge the kernel-level entry uses for a padded size K and dtype.
 int gemm_pick_tile(int64_t K, int dtype);
-int64_t gemm_padded_size(int64_t n);
+// Whether plain products of an n x n matrix use the 256 tile, and the padded
+// size of its work matrices (a multiple of every tile it runs with; `big`:
+// the 256 tile is used).
+bool gemm_use_big(int64_t n, int dtype);
+int64_t gemm_padded_size(int64_t n, bool big);
+// Tile lists of a plan: `big` (256 tiles of plain products, whole rounds of
+// one workgroup per CU), `small_plain` (the rest of the plain products as 128
+// tiles), `small_all` (every matrix's full triangle of 128 tiles, for split
+// products). np: padded orders; big: gemm_use_big per matrix; cus: CU count.
+struct TileLists {
+    std::vector<WorkItem> big, small_plain, small_all;
+};
+void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out);
+// Incremented whenever a tuning hook changes the tile choice.
+int gemm_tile_generation();
+// CU count the tail rule uses (the device's unless the tuning hook set one).
+int gemm_tail_cus(int device_cus);
+// Tuning hook: size from which plain products use the 256 tile, and the CU
+// count of the tail rule (0: the device's).
+void gemm_set_big_tiles(int64_t min_n, int tail_cus);
 // Tuning hook: force the tile edge (0 restores the automatic choice).
 void gemm_set_tile_override(int bm);
 // Tuning hook: blocking of the tile schedule (H tile rows x W tile columns).

@@ -119,24 +119,39 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
 
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
+// Plain products of this matrix run on 256 tiles (FP32_EMU has no plain
+// products: every stage and the final product are split).
+bool plan_big(int64_t n, const StagePlan &p) {
+    const bool all_split = p.split_final && p.split_mask == ((1u << p.T) - 1);
+    return !all_split && gemm_use_big(n, p.dtype);
+}
+
 size_t align256(size_t b) { return (size_t)round_up((int64_t)b, 256); }
+
+// Leading-dimension padding of the work matrices (elements). A row stride
+// that is a multiple of 1024 elements (e.g. n_p = 10240) maps the rows a tile
+// streams onto few memory channels: split products at n_p = 10240 ran 13%
+// slower than at 10112. Such strides get 128 more elements; others (10112,
+// 10368) are left alone, which measured best.
+static int64_t g_ld_pad = 128;
 
 // One matrix's workspace inside the arena.
 struct MatLayout {
-    int64_t n, np;
+    int64_t n, np, ldw;
     size_t off_scal, off_lz, off_mat, mat_bytes, total;
 };
 
 MatLayout mat_layout(int64_t n, const StagePlan &p, int steps) {
     MatLayout L{};
     L.n = n;
-    L.np = gemm_padded_size(n);
+    L.np = gemm_padded_size(n, plan_big(n, p));
+    L.ldw = (L.np >= 2048 && L.np % 1024 == 0) ? L.np + g_ld_pad : L.np;
     const bool split = p.split_mask != 0 || p.split_final;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     L.off_scal = take(sizeof(Scalars));
     L.off_lz = take(sizeof(double) * lanczos_work_doubles(n, steps));
-    L.mat_bytes = align256(elt_size(p.dtype) * (size_t)L.np * (size_t)L.np);
+    L.mat_bytes = align256(elt_size(p.dtype) * (size_t)L.ldw * (size_t)L.np);
     L.off_mat = take(L.mat_bytes * 4 * (split ? 2 : 1));
     L.total = off;
     return L;
@@ -149,9 +164,14 @@ struct Plan {
     std::vector<int64_t> ns;
     // layout
     StagePlan sp;
-    size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[2] = {0, 0}, total = 0;
-    int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[2] = {0, 0};
-    int gemm_bm[2] = {256, 128};
+    // GEMM work lists: [0] 256 tiles of plain products, [1] 128 tiles of plain
+    // products, [2] 128 tiles of split products (gemm_tile_lists)
+    size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[3] = {0, 0, 0}, total = 0;
+    int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[3] = {0, 0, 0};
+    int gemm_bm[3] = {256, 128, 128};
+    TileLists tiles;
+    int cus = 256;       // compute units the tail split is sized for
+    int tile_gen = -1;   // tuning generation the tile lists were built for
     std::vector<size_t> mat_off;
     std::vector<MatLayout> mats;
     // arena the device tables were built for
@@ -167,7 +187,7 @@ struct Plan {
     // rq: the stage plan of the request (mode, split choices)
     bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
-               ns == n;
+               ns == n && tile_gen == gemm_tile_generation();
     }
 };
 
@@ -176,17 +196,21 @@ void layout_plan(Plan &P) {
     P.mats.clear();
     P.mat_off.clear();
     P.n_vec = P.n_symv = P.n_cast = 0;
-    P.n_gemm[0] = P.n_gemm[1] = 0;
+    std::vector<int64_t> nps;
+    std::vector<bool> big;
     for (int64_t n : P.ns) {
         P.mats.push_back(mat_layout(n, P.sp, P.steps));
         const MatLayout &L = P.mats.back();
         P.n_vec += vec_block_count(n);
         P.n_symv += symv_tile_count(n);
         P.n_cast += cast_tile_count(L.np);
-        const int bm = gemm_pick_tile(L.np, P.sp.dtype);
-        const int64_t T = L.np / bm;
-        P.n_gemm[bm == 256 ? 0 : 1] += T * (T + 1) / 2;
+        nps.push_back(L.np);
+        big.push_back(plan_big(n, P.sp));
     }
+    gemm_tile_lists(nps, big, P.cus, P.tiles);
+    P.n_gemm[0] = (int64_t)P.tiles.big.size();
+    P.n_gemm[1] = (int64_t)P.tiles.small_plain.size();
+    P.n_gemm[2] = (int64_t)P.tiles.small_all.size();
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     P.off_desc = take(sizeof(MatDesc) * M);
@@ -194,8 +218,7 @@ void layout_plan(Plan &P) {
     P.off_wvec = take(sizeof(WorkItem) * (size_t)P.n_vec);
     P.off_wsymv = take(sizeof(WorkItem) * (size_t)P.n_symv);
     P.off_wcast = take(sizeof(WorkItem) * (size_t)P.n_cast);
-    P.off_wgemm[0] = take(sizeof(WorkItem) * (size_t)P.n_gemm[0]);
-    P.off_wgemm[1] = take(sizeof(WorkItem) * (size_t)P.n_gemm[1]);
+    for (int c = 0; c < 3; ++c) P.off_wgemm[c] = take(sizeof(WorkItem) * (size_t)P.n_gemm[c]);
     for (const MatLayout &L : P.mats) P.mat_off.push_back(take(L.total));
     P.total = off;
 }
@@ -207,7 +230,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     const size_t M = P.ns.size();
     uint8_t *b = (uint8_t *)base;
     std::vector<MatDesc> desc(M);
-    std::vector<WorkItem> wv, wt, wc, wg[2];
+    std::vector<WorkItem> wv, wt, wc;
     const bool split = P.sp.split_mask != 0 || P.sp.split_final;
     for (size_t m = 0; m < M; ++m) {
         const MatLayout &L = P.mats[m];
@@ -216,7 +239,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         memset(&d, 0, sizeof(d));
         d.n = L.n;
         d.np = L.np;
-        d.ldw = L.np;
+        d.ldw = L.ldw;
         d.scal = (Scalars *)(mb + L.off_scal);
         fill_lanczos_desc(d, (double *)(mb + L.off_lz), L.n, P.steps);
         for (int k = 0; k < 4; ++k) {
@@ -226,9 +249,8 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < cast_tile_count(L.np); ++i) wc.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
-        const int bm = gemm_pick_tile(L.np, P.sp.dtype);
-        append_tile_order(wg[bm == 256 ? 0 : 1], (uint32_t)m, (int)(L.np / bm));
     }
+    const std::vector<WorkItem> *wg[3] = {&P.tiles.big, &P.tiles.small_plain, &P.tiles.small_all};
     if (hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
     auto up = [&](size_t off, const void *src, size_t bytes) {
         return bytes == 0 || hipMemcpy(b + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
@@ -236,8 +258,9 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     if (!up(P.off_desc, desc.data(), sizeof(MatDesc) * M) || !up(P.off_wvec, wv.data(), sizeof(WorkItem) * wv.size()) ||
         !up(P.off_wsymv, wt.data(), sizeof(WorkItem) * wt.size()) ||
         !up(P.off_wcast, wc.data(), sizeof(WorkItem) * wc.size()) ||
-        !up(P.off_wgemm[0], wg[0].data(), sizeof(WorkItem) * wg[0].size()) ||
-        !up(P.off_wgemm[1], wg[1].data(), sizeof(WorkItem) * wg[1].size()))
+        !up(P.off_wgemm[0], wg[0]->data(), sizeof(WorkItem) * wg[0]->size()) ||
+        !up(P.off_wgemm[1], wg[1]->data(), sizeof(WorkItem) * wg[1]->size()) ||
+        !up(P.off_wgemm[2], wg[2]->data(), sizeof(WorkItem) * wg[2]->size()))
         return PSDPROJ_ERR_HIP;
     P.base = base;
     return PSDPROJ_OK;
@@ -377,7 +400,10 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         if (g_timer.on && (rec.a = g_timer.take()) && (rec.b = g_timer.take())) {
             if (hipEventRecord(rec.a, s) != hipSuccess) return hipErrorUnknown;
         }
-        for (int c = 0; c < 2; ++c) {
+        // plain products: the 256-tile rounds, then the 128 tiles; split
+        // products: the 128-tile lists
+        const bool pair = ls || rs;
+        for (int c = pair ? 2 : 0; c < (pair ? 3 : 2); ++c) {
             if (!P.n_gemm[c]) continue;
             g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
             const hipError_t r = gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], P.n_gemm[c], s);
@@ -437,6 +463,11 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
         P->split_mask = sp.split_mask;
         P->split_final = sp.split_final;
         P->ns = ns;
+        P->tile_gen = gemm_tile_generation();
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        P->cus = gemm_tail_cus(cus);
         layout_plan(*P);
         if (pool.plan && hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
         pool.plan = std::move(P);
@@ -643,6 +674,9 @@ int psdproj_release(void) {
     return PSDPROJ_OK;
 }
 
+static int64_t g_big_min_hook = 6144;
+static int g_tail_cus_hook = 0;
+
 int psdproj_gemm_timing_start(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &r : g_timer.pending) {
@@ -680,6 +714,26 @@ int psdproj_tune(const char *key, int64_t value) {
     if (!strcmp(key, "gemm_tile")) {
         if (value != 0 && value != 128 && value != 256) return PSDPROJ_ERR_INVALID_ARG;
         gemm_set_tile_override((int)value);
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "work_ld_pad")) {  // leading-dimension padding of large work matrices
+        if (value < 0 || value > 4096 || value % 64) return PSDPROJ_ERR_INVALID_ARG;
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (hipDeviceSynchronize() != hipSuccess) return PSDPROJ_ERR_HIP;  // plans in flight
+        g_ld_pad = value;
+        for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "gemm_big_min")) {  // plain products of n >= value use the 256 tile
+        if (value < 1) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_big_tiles(value, g_tail_cus_hook);
+        g_big_min_hook = value;
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "gemm_tail_cus")) {  // CU count of the tail rule (0: the device's)
+        if (value < 0 || value > 65536) return PSDPROJ_ERR_INVALID_ARG;
+        g_tail_cus_hook = (int)value;
+        gemm_set_big_tiles(g_big_min_hook, g_tail_cus_hook);
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_block")) {  // value = H * 256 + W

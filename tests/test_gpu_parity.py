@@ -210,3 +210,30 @@ def test_batched_equals_single():
     torch.cuda.synchronize()
     for a, b in zip(outs, singles):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp8_fp16_split"])
+def test_mixed_tile_sizes_bitwise_equal(mode):
+    """Plain products on whole rounds of 256 tiles plus a tail of 128 tiles
+    (forced at a small size: 256 tiles from n = 512, a tail rule for 8 CUs)
+    give the same bits as 128 tiles only, and match the oracle."""
+    import torch
+    X32 = inputs.goe(1500, 21)
+    Xg = to_dev(X32)
+    say("mixed tiles", mode)
+    try:
+        P.tune("gemm_tile", 128)
+        ref_t, info_t = P.project_ex(Xg, mode=mode)
+        P.tune("gemm_tile", 0)
+        P.tune("gemm_big_min", 512)
+        P.tune("gemm_tail_cus", 8)     # 21 tiles of 256: 16 in rounds, 5 as 128 tiles
+        mix_t, _ = P.project_ex(Xg, mode=mode)
+        torch.cuda.synchronize()
+    finally:
+        P.tune("gemm_tail_cus", 0)
+        P.tune("gemm_big_min", 6144)
+        P.tune("gemm_tile", 0)
+    assert torch.equal(ref_t, mix_t)
+    info = P.read_info(info_t)
+    ref, _ = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"])
+    assert rel_fro(mix_t.cpu().numpy(), ref) <= TOL_POLY[mode]
