@@ -121,10 +121,12 @@ def gemm_roofline(X, out, opts, n, mode, stream):
     for v in classes.values():
         v["tflops_per_product_equivalent"] = flops / (v["avg_ms"] * 1e-3) / 1e12
     tr = measured_traffic(mode) if n == 10000 else None
-    res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection launches)", "bound": "mfma",
+    res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection products; from n = 6144 one "
+                     "product is a launch of 256 x 256 tiles over whole rounds plus a launch of the 128 x 128 tail)",
+           "bound": "mfma",
            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
            "traffic": tr["traffic_bytes_per_launch"] if tr else None, "ms_per_launch": ms, "flops_per_launch": flops,
-           "launches": cls["plain"]["launches"], "n_padded": (n + 127) // 128 * 128, "product_classes": classes}
+           "launches": cls["plain"]["launches"], "product_classes": classes}
     if tr:
         res["traffic_detail"] = {"unit": "bytes per launch", "fetch": tr["fetch_bytes_per_launch"],
                                  "write": tr["write_bytes_per_launch"],
