@@ -170,7 +170,6 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int NSUB = PAIR8 ? TB / 64 : TB / 32;
     static_assert(NSUB >= 1, "at least one K-unit per tile");
     static_assert(!COMB || NCH == 8, "combined rows are 128 bytes");
-    static_assert(!PAIR8 || BM == 128, "FP8-pair products use the 128 tile");
     constexpr int WM = BM / 2;                // wave tile edge
     constexpr int MI = WM / 32;
     static_assert(BM * NCH % kThreads == 0 && WM % 32 == 0, "tile shape");
@@ -405,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 // accumulator still sees substep 0, 1, then the cross terms
                 const Frag &f = fr[sub & 1];
                 __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<4 * MI>();
+                wait_lgkmcnt<(4 * MI < 15 ? 4 * MI : 15)>();
 #pragma unroll
                 for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -587,7 +586,6 @@ void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T) {
 // n = 10^4 (37.1 vs 38.0 ms for a plain FP16 projection), so it is the default;
 // the 256 tile remains available through the tuning hook.
 int gemm_pick_tile(int64_t K, int dtype) {
-    if (dtype == DT_F16X8) return 128;  // FP8-pair kernels exist for the 128 tile only
     const int o = g_tile_override;
     if (o && K % o == 0) return o;
     return 128;
@@ -607,6 +605,19 @@ bool gemm_use_big(int64_t n, int dtype) {
     return dtype != DT_F32 && n >= g_big_min;
 }
 int gemm_tail_cus(int device_cus) { return g_tail_cus > 0 ? g_tail_cus : device_cus; }
+
+// Split products are bound by operand movement as well, so the 256 tile pays
+// for them too (per-dtype switch for the tuning hook).
+static int g_split_big = 3;
+bool gemm_split_big(int dtype) {
+    if (g_tile_override == 128) return false;
+    if (dtype == DT_F16X8) return (g_split_big & 2) != 0;
+    return dtype != DT_F32 && (g_split_big & 1) != 0;
+}
+void gemm_set_split_big(int mask) {
+    g_split_big = mask;
+    ++g_tile_gen;
+}
 
 // Padded order of the work matrices: a multiple of 256 where the 256 tile is
 // used, else of 128 (or of the override). Any choice gives bitwise-identical
@@ -677,7 +688,13 @@ static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s) {
 
 template <int EPI>
 static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s) {
-    if (pair) return bm == 128 ? launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s) : hipErrorInvalidValue;
+    if (pair) {
+        switch (bm) {
+            case 256: return launch_bm<f16, true, true, EPI, 256, true>(g, ntiles, s);
+            case 128: return launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (bm) {
         case 256: return launch_bm<f16, false, false, EPI, 256, true>(g, ntiles, s);
         case 128: return launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s);

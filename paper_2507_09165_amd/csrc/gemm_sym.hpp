@@ -58,6 +58,11 @@ int gemm_tail_cus(int device_cus);
 // Tuning hook: size from which plain products use the 256 tile, and the CU
 // count of the tail rule (0: the device's).
 void gemm_set_big_tiles(int64_t min_n, int tail_cus);
+// Whether split products of matrices that use the 256 tile use it too (else
+// they run the 128-tile list). Tuning hook: mask, bit 0 FP16/BF16 pairs, bit 1
+// FP8 pairs.
+bool gemm_split_big(int dtype);
+void gemm_set_split_big(int mask);
 // Tuning hook: force the tile edge (0 restores the automatic choice).
 void gemm_set_tile_override(int bm);
 // Tuning hook: blocking of the tile schedule (H tile rows x W tile columns).

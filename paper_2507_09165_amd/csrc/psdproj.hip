@@ -119,11 +119,12 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
 
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
-// Plain products of this matrix run on 256 tiles (FP32_EMU has no plain
-// products: every stage and the final product are split).
+// Products of this matrix run on 256 tiles: plain ones whenever the size
+// calls for it, split ones where the split switch also allows it (FP32_EMU
+// has no plain products: every stage and the final product are split).
 bool plan_big(int64_t n, const StagePlan &p) {
     const bool all_split = p.split_final && p.split_mask == ((1u << p.T) - 1);
-    return !all_split && gemm_use_big(n, p.dtype);
+    return gemm_use_big(n, p.dtype) && (!all_split || gemm_split_big(p.dtype));
 }
 
 size_t align256(size_t b) { return (size_t)round_up((int64_t)b, 256); }
@@ -172,6 +173,7 @@ struct Plan {
     TileLists tiles;
     int cus = 256;       // compute units the tail split is sized for
     int tile_gen = -1;   // tuning generation the tile lists were built for
+    bool split_big = false;  // split products use the 256/128 lists too
     std::vector<size_t> mat_off;
     std::vector<MatLayout> mats;
     // arena the device tables were built for
@@ -400,10 +402,10 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         if (g_timer.on && (rec.a = g_timer.take()) && (rec.b = g_timer.take())) {
             if (hipEventRecord(rec.a, s) != hipSuccess) return hipErrorUnknown;
         }
-        // plain products: the 256-tile rounds, then the 128 tiles; split
-        // products: the 128-tile lists
-        const bool pair = ls || rs;
-        for (int c = pair ? 2 : 0; c < (pair ? 3 : 2); ++c) {
+        // the 256-tile rounds, then the 128 tiles; split products without
+        // the 256 tile: the list of 128 tiles only
+        const bool small = (ls || rs) && !P.split_big;
+        for (int c = small ? 2 : 0; c < (small ? 3 : 2); ++c) {
             if (!P.n_gemm[c]) continue;
             g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
             const hipError_t r = gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], P.n_gemm[c], s);
@@ -464,6 +466,7 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
         P->split_final = sp.split_final;
         P->ns = ns;
         P->tile_gen = gemm_tile_generation();
+        P->split_big = gemm_split_big(sp.dtype);
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
@@ -734,6 +737,11 @@ int psdproj_tune(const char *key, int64_t value) {
         if (value < 0 || value > 65536) return PSDPROJ_ERR_INVALID_ARG;
         g_tail_cus_hook = (int)value;
         gemm_set_big_tiles(g_big_min_hook, g_tail_cus_hook);
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "gemm_split_big")) {  // bit 0: FP16/BF16 pairs, bit 1: FP8 pairs on 256 tiles
+        if (value < 0 || value > 3) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_split_big((int)value);
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_block")) {  // value = H * 256 + W

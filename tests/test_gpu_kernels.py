@@ -187,6 +187,32 @@ def test_sym_gemm_pair8(n_p):
     np.testing.assert_array_equal(tab[lc], tab[lc.T])
 
 
+@pytest.mark.parametrize("n_p", [512, 768])
+def test_sym_gemm_pair8_tile_shapes_agree(n_p):
+    """The FP8-pair product on 128 and on 256 tiles: bitwise-identical FP16
+    parts and codes (every element takes its 32-K units in the same order)."""
+    import torch
+    say("sym_gemm pair8 tiles", n_p)
+    A = inputs.goe(n_p, 73, np.float64)
+    Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)
+    Lh, Lx, _ = _pair8(A, 7)
+    Rh, Rx, _ = _pair8(Bm, 5)
+    outs = []
+    try:
+        for tile in (128, 256):
+            P.tune("gemm_tile", tile)
+            D = torch.zeros_like(Lh)
+            Dx = torch.zeros(n_p, n_p, dtype=torch.uint8, device=dev())
+            P.sym_gemm_pair8(Lh, Rh, D, Lx=Lx, Rx=Rx, C0=Lh, C0x=Lx, Dx=Dx, alpha=0.5, beta=-1.25,
+                             exps=(7, 5, 7, 3))
+            torch.cuda.synchronize()
+            outs.append((D.cpu(), Dx.cpu()))
+    finally:
+        P.tune("gemm_tile", 0)
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
 def test_sym_gemm_pair8_plain_operands_pair_output():
     """Unsplit operands with a pair addend and a pair output (the product that
     feeds the first split stage)."""
