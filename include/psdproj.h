@@ -145,15 +145,20 @@ const char *psdproj_status_string(int status);
 
 /* Tuning hook (process-wide, not thread-safe against concurrent launches).
  * By default the products of matrices with n >= 6144 (FP16/BF16 modes) run
- * their whole rounds of 256 x 256 tiles (one workgroup per CU) and the last
- * partial round as 128 x 128 tiles; smaller matrices run 128 tiles. Any
- * tiling gives bitwise-identical results.
+ * their whole rounds of 256 x 256 tiles (one workgroup per CU). The tiles of
+ * a last partial round are cut into K-chunks that run side by side (FP32
+ * partials summed in chunk order by a fixup) when they fill at most half the
+ * CUs, else they run as 128 x 128 tiles; smaller matrices run 128 tiles.
+ * Results are deterministic and do not depend on the other matrices of a
+ * batch; they depend on the CU count and these settings only through the
+ * rounding of the K-split tiles (every other tiling gives the same bits).
  * "gemm_tile" = 0 (automatic), 128 (128 tiles only) or 256 (256 tiles for
  * all such products, no tail split; the kernel-level entries use it when n_p
  * is a multiple of 256); "gemm_big_min" = n from which products use 256
  * tiles; "gemm_split_big" = mask of the split products that follow that rule
  * (bit 0 FP16/BF16 pairs, bit 1 FP8 pairs; default 3; the others run 128
- * tiles); "gemm_tail_cus" = CU count the tail rule assumes (0: the
+ * tiles); "gemm_ksplit" = most K-chunks per tail tile (default 8; 1 never
+ * splits); "gemm_tail_cus" = CU count the tail rule assumes (0: the
  * device's); "work_ld_pad" = elements added to the leading dimension of work
  * matrices whose padded order n_p >= 2048 is a multiple of 1024 (default 128;
  * multiple of 64; synchronises the device); "gemm_block" = H * 256 + W sets the blocking of the GEMM tile

@@ -148,7 +148,15 @@ __device__ __forceinline__ void wait_lgkmcnt() {
 // panels of 128-byte rows hold a split K-tile: conflict-free reads at two
 // workgroups per CU, where four panels of 64-byte rows cost 6.7 LDS cycles
 // per read.
-template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8>
+//
+// KS: 0 = whole tile; 1 = one K-chunk of a split tile (entry {matrix, tile,
+// chunk | chunks << 8, partial}; the raw FP32 accumulators go to the partial
+// buffer, no epilogue); 2 = fixup of a split tile (entry {matrix, tile,
+// chunks << 8, first partial}; sums the chunks' partials in chunk order, then
+// the epilogue). A fixup workgroup covers one 32 x 32 MFMA block (mi, ni) of
+// every wave, so a tile's fixup is spread over MI^2 workgroups. The split tiles are the few that would otherwise leave most CUs
+// idle in a last, partial round of 256 tiles.
+template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8, int KS>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     static_assert(!X8 || (sizeof(T) == 2 && LS == RS), "FP8 pairs: FP16 hi, both operands split");
     constexpr bool PAIR8 = X8 && LS;          // FP8 cross terms in the main loop
@@ -176,7 +184,21 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     static_assert(NST >= 2, "at least two LDS stages");
     __shared__ __attribute__((aligned(16))) uint8_t smem[NST * STAGE];
 
-    const WorkItem tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    constexpr int MB = (BM / 64) * (BM / 64);  // MFMA blocks per wave (MI^2)
+    static_assert(MB == MI * MI, "fixup blocks");
+    WorkItem tv;
+    int kchunk = 0, kchunks = 1, fblk = 0;
+    uint32_t part = 0;
+    if constexpr (KS == 0) {
+        tv = g.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    } else {
+        if constexpr (KS == 2) fblk = (int)(blockIdx.x % MB);
+        const uint4 e = g.split[KS == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)(blockIdx.x / MB)];
+        tv = WorkItem{e.x, e.y};
+        kchunk = (int)(e.z & 255u);
+        kchunks = (int)(e.z >> 8);
+        part = e.w;
+    }
     const MatDesc &dm = g.D[tv.x];
     const int bi = (int)(tv.y & 0xFFFFu), bj = (int)(tv.y >> 16);
     const int64_t i0 = (int64_t)bi * BM;
@@ -262,192 +284,229 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     };
     static_assert(PAIR8 || RPL * NCH == 64, "lane layout");
 
-    f32x16 acc[MI][MI];
+    // accumulators: MI x MI blocks of 32 x 32 per wave; the fixup holds only
+    // its block (fmi, fni), as a 1 x 1 array
+    constexpr int MIE = KS == 2 ? 1 : MI;
+    const int fmi = fblk / MI, fni = fblk % MI;
+    f32x16 acc[MIE][MIE];
 #pragma unroll
-    for (int mi = 0; mi < MI; ++mi)
+    for (int mi = 0; mi < MIE; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < MI; ++ni)
+        for (int ni = 0; ni < MIE; ++ni)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[mi][ni][e] = 0.0f;
-
-    // fragment row offsets inside a panel, and the row's swizzle key
-    int roff_a[MI], roff_b[MI], key_a[MI], key_b[MI];
-    int ra_[MI], rb_[MI];
-#pragma unroll
-    for (int m = 0; m < MI; ++m) {
-        const int ra = wr + m * 32 + (lane & 31), rb = wc + m * 32 + (lane & 31);
-        ra_[m] = ra;
-        rb_[m] = rb;
-        roff_a[m] = ra * ROWB;
-        roff_b[m] = rb * ROWB;
-        key_a[m] = swz<NCH>(ra, 0);
-        key_b[m] = swz<NCH>(rb, 0);
-    }
-
-    const int64_t nk = dm.np / BK;
-    // Fragments of one K-unit, [part][MFMA block m]. Plain and FP16 pairs:
-    // one part per operand panel. FP8 pairs: L_hi (two 16-K substeps),
-    // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo).
-    constexpr int NFP = PAIR8 ? 6 : NLP + NRP;
-    typedef u32x4 Frag[NFP][MI];
-    // E8M0 scale codes 2^(c - 127), replicated into every byte
-    const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
-    const int sb8 = PAIR8 ? (int)((uint32_t)(127 - g.es_r) * 0x01010101u) : 0;
-    const float cva = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_l) : 0.0f;  // hi-code conversion scales
-    const float cvb = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_r) : 0.0f;
-    auto rd = [&](const uint8_t *base, int pan, bool b_side, int m, int c) -> u32x4 {
-        const int ro = b_side ? roff_b[m] : roff_a[m], key = b_side ? key_b[m] : key_a[m];
-        return *(const u32x4 *)(base + pan * PANEL + ro + ((c ^ key) << 4));
+    // partial buffers: one 16-float block of (mi, ni) per thread, stored as
+    // four float4 rows of kThreads entries (coalesced)
+    auto part_ptr = [&](uint32_t p, int mi, int ni, int q) -> f32x4 * {
+        return (f32x4 *)g.part + (((size_t)p * MI * MI + mi * MI + ni) * 4 + q) * kThreads + threadIdx.x;
     };
-    auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
-        const int hg = lane >> 5;
-        if constexpr (PAIR8) {
-            // [0] L hi substep 0, [1] L hi substep 1, [2] L codes, [3..5] R;
-            // issued in groups (substep 0, substep 1, codes) so the MFMAs can
-            // start on each group as it lands
-            const uint8_t *lh = base, *ll = base + P8HI, *rh = base + P8HI + P8LO, *rl = rh + P8HI;
+    if constexpr (KS == 2) {
+        for (int c = 0; c < kchunks; ++c)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 v = *part_ptr(part + c, fmi, fni, q);
 #pragma unroll
-                for (int m = 0; m < MI; ++m)
-                    f[h][m] = *(const u32x4 *)(lh + ra_[m] * 64 + (((2 * h + hg) ^ ((ra_[m] >> 2) & 3)) << 4));
-#pragma unroll
-                for (int m = 0; m < MI; ++m)
-                    f[3 + h][m] = *(const u32x4 *)(rh + rb_[m] * 64 + (((2 * h + hg) ^ ((rb_[m] >> 2) & 3)) << 4));
-                __builtin_amdgcn_sched_barrier(0);
+                for (int e = 0; e < 4; ++e) acc[0][0][4 * q + e] += v[e];
             }
+    } else {
+        // fragment row offsets inside a panel, and the row's swizzle key
+        int roff_a[MI], roff_b[MI], key_a[MI], key_b[MI];
+        int ra_[MI], rb_[MI];
 #pragma unroll
-            for (int m = 0; m < MI; ++m) {
-                f[2][m] = *(const u32x4 *)(ll + ra_[m] * 32 + ((hg ^ ((ra_[m] >> 3) & 1)) << 4));
-                f[5][m] = *(const u32x4 *)(rl + rb_[m] * 32 + ((hg ^ ((rb_[m] >> 3) & 1)) << 4));
-            }
-            return;
-        } else if constexpr (COMB) {
-#pragma unroll
-            for (int m = 0; m < MI; ++m) {
-                f[0][m] = rd(base, 0, false, m, 2 * sub + hg);
-                f[1][m] = rd(base, 0, false, m, HCH + 2 * sub + hg);
-                f[2][m] = rd(base, 1, true, m, 2 * sub + hg);
-                f[3][m] = rd(base, 1, true, m, HCH + 2 * sub + hg);
-            }
-            return;
+        for (int m = 0; m < MI; ++m) {
+            const int ra = wr + m * 32 + (lane & 31), rb = wc + m * 32 + (lane & 31);
+            ra_[m] = ra;
+            rb_[m] = rb;
+            roff_a[m] = ra * ROWB;
+            roff_b[m] = rb * ROWB;
+            key_a[m] = swz<NCH>(ra, 0);
+            key_b[m] = swz<NCH>(rb, 0);
         }
-        const int cl = 2 * sub + hg;
+
+        // K-tiles of this workgroup: all, or chunk kchunk of kchunks
+        const int64_t nk_all = dm.np / BK;
+        const int64_t kch = (nk_all + kchunks - 1) / kchunks;
+        const int64_t kb = kchunk * kch < nk_all ? kchunk * kch : nk_all;
+        const int64_t ke = kb + kch < nk_all ? kb + kch : nk_all;
+        // Fragments of one K-unit, [part][MFMA block m]. Plain and FP16 pairs:
+        // one part per operand panel. FP8 pairs: L_hi (two 16-K substeps),
+        // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo).
+        constexpr int NFP = PAIR8 ? 6 : NLP + NRP;
+        typedef u32x4 Frag[NFP][MI];
+        // E8M0 scale codes 2^(c - 127), replicated into every byte
+        const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
+        const int sb8 = PAIR8 ? (int)((uint32_t)(127 - g.es_r) * 0x01010101u) : 0;
+        const float cva = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_l) : 0.0f;  // hi-code conversion scales
+        const float cvb = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_r) : 0.0f;
+        auto rd = [&](const uint8_t *base, int pan, bool b_side, int m, int c) -> u32x4 {
+            const int ro = b_side ? roff_b[m] : roff_a[m], key = b_side ? key_b[m] : key_a[m];
+            return *(const u32x4 *)(base + pan * PANEL + ro + ((c ^ key) << 4));
+        };
+        auto load_frags = [&](const uint8_t *base, int sub, Frag &f) {
+            const int hg = lane >> 5;
+            if constexpr (PAIR8) {
+                // [0] L hi substep 0, [1] L hi substep 1, [2] L codes, [3..5] R;
+                // issued in groups (substep 0, substep 1, codes) so the MFMAs can
+                // start on each group as it lands
+                const uint8_t *lh = base, *ll = base + P8HI, *rh = base + P8HI + P8LO, *rl = rh + P8HI;
 #pragma unroll
-        for (int p = 0; p < NLP; ++p)
+                for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int m = 0; m < MI; ++m)
-                f[p][m] = *(const u32x4 *)(base + p * PANEL + roff_a[m] + ((cl ^ key_a[m]) << 4));
+                    for (int m = 0; m < MI; ++m)
+                        f[h][m] = *(const u32x4 *)(lh + ra_[m] * 64 + (((2 * h + hg) ^ ((ra_[m] >> 2) & 3)) << 4));
 #pragma unroll
-        for (int p = 0; p < NRP; ++p)
+                    for (int m = 0; m < MI; ++m)
+                        f[3 + h][m] = *(const u32x4 *)(rh + rb_[m] * 64 + (((2 * h + hg) ^ ((rb_[m] >> 2) & 3)) << 4));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
 #pragma unroll
-            for (int m = 0; m < MI; ++m)
-                f[NLP + p][m] = *(const u32x4 *)(base + (NLP + p) * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
-    };
-    auto mfmas = [&](const Frag &f) {
+                for (int m = 0; m < MI; ++m) {
+                    f[2][m] = *(const u32x4 *)(ll + ra_[m] * 32 + ((hg ^ ((ra_[m] >> 3) & 1)) << 4));
+                    f[5][m] = *(const u32x4 *)(rl + rb_[m] * 32 + ((hg ^ ((rb_[m] >> 3) & 1)) << 4));
+                }
+                return;
+            } else if constexpr (COMB) {
+#pragma unroll
+                for (int m = 0; m < MI; ++m) {
+                    f[0][m] = rd(base, 0, false, m, 2 * sub + hg);
+                    f[1][m] = rd(base, 0, false, m, HCH + 2 * sub + hg);
+                    f[2][m] = rd(base, 1, true, m, 2 * sub + hg);
+                    f[3][m] = rd(base, 1, true, m, HCH + 2 * sub + hg);
+                }
+                return;
+            }
+            const int cl = 2 * sub + hg;
+#pragma unroll
+            for (int p = 0; p < NLP; ++p)
+#pragma unroll
+                for (int m = 0; m < MI; ++m)
+                    f[p][m] = *(const u32x4 *)(base + p * PANEL + roff_a[m] + ((cl ^ key_a[m]) << 4));
+#pragma unroll
+            for (int p = 0; p < NRP; ++p)
+#pragma unroll
+                for (int m = 0; m < MI; ++m)
+                    f[NLP + p][m] = *(const u32x4 *)(base + (NLP + p) * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
+        };
+        auto mfmas = [&](const Frag &f) {
+#pragma unroll
+            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < MI; ++ni) {
+                    if constexpr (PAIR8) {
+                        mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                        mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                        mma_x8(acc[mi][ni], hi8_codes(f[0][mi], f[1][mi], cva), f[2][mi], f[5][ni],
+                               hi8_codes(f[3][ni], f[4][ni], cvb), sa8, sb8);
+                    } else if constexpr (LS || RS) {
+                        mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
+                        if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
+                        if constexpr (LS) mma(acc[mi][ni], f[1][mi], f[NLP][ni], T{});
+                    } else {
+                        mma(acc[mi][ni], f[0][mi], f[NLP][ni], T{});
+                    }
+                }
+        };
+        // ds_read_b128 per K-unit; the counter holds 15 at most, and a wait for
+        // <= 15 outstanding is still enough when more were issued after the ones
+        // needed (in-order return)
+        constexpr int NDS = NFP * MI < 15 ? NFP * MI : 15;
+        Frag fr[2];
+        // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
+        // Every wave issues exactly NLD loads per iteration (the index is clamped
+        // at the end), so "tile kt+1 has landed" is vmcnt <= NLD * (NST - 2).
+        if (ke > kb) {
+#pragma unroll
+            for (int t = 0; t < NST - 1; ++t) issue_loads(kb + t < ke ? kb + t : ke - 1, t);
+            wait_vmcnt<NLD * (NST - 2)>();
+            __builtin_amdgcn_s_barrier();
+            load_frags(smem, 0, fr[0]);
+            // Drain every LDS and scalar-memory access of the prologue, so that no
+            // scalar load (which may return out of order) is pending in the loop and
+            // the counted LDS waits below are the only ones needed.
+            wait_lgkmcnt<0>();
+            for (int64_t kt = kb; kt < ke; ++kt) {
+                const int64_t kr = kt - kb;  // ring position
+                const int st = (int)(kr % NST);
+                const uint8_t *base = smem + st * STAGE;
+                // stage (kr - 1) mod NST was last read in iteration kt - 1, which every
+                // wave finished before the barrier that ended it
+                const int64_t tn = kt + NST - 1;
+                issue_loads(tn < ke ? tn : ke - 1, (int)((kr + NST - 1) % NST));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int sub = 0; sub < NSUB; ++sub) {
+                    // next substep's fragments first, then this substep's MFMAs on
+                    // fragments loaded one substep earlier: wait only for those (the
+                    // NDS reads just issued may stay in flight under the MFMAs)
+                    if (sub + 1 < NSUB) {
+                        load_frags(base, sub + 1, fr[(sub + 1) & 1]);
+                        __builtin_amdgcn_sched_barrier(0);
+                        wait_lgkmcnt<NDS>();
+                        mfmas(fr[sub & 1]);
+                    } else if constexpr (PAIR8) {
+                        // the unit's reads were issued in groups (substep 0, substep
+                        // 1, codes): start on each group as it lands; every
+                        // accumulator still sees substep 0, 1, then the cross terms
+                        const Frag &f = fr[sub & 1];
+                        __builtin_amdgcn_sched_barrier(0);
+                        wait_lgkmcnt<(4 * MI < 15 ? 4 * MI : 15)>();
+#pragma unroll
+                        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                        __builtin_amdgcn_sched_barrier(0);
+                        wait_lgkmcnt<2 * MI>();
+#pragma unroll
+                        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                        u32x4 ha[MI], hb[MI];
+#pragma unroll
+                        for (int m = 0; m < MI; ++m) {
+                            ha[m] = hi8_codes(f[0][m], f[1][m], cva);
+                            hb[m] = hi8_codes(f[3][m], f[4][m], cvb);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        wait_lgkmcnt<0>();
+#pragma unroll
+                        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < MI; ++ni) mma_x8(acc[mi][ni], ha[mi], f[2][mi], f[5][ni], hb[ni], sa8, sb8);
+                    } else {
+                        __builtin_amdgcn_sched_barrier(0);
+                        wait_lgkmcnt<0>();
+                        mfmas(fr[sub & 1]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // Tile kt + 1 landed for this wave, then (barrier) for all waves. A
+                // plain s_barrier: a fenced __syncthreads would wait for every
+                // outstanding load (vmcnt(0)) and undo the prefetch. Every ds_read of
+                // the stage about to be refilled was consumed by an MFMA above.
+                wait_vmcnt<NLD * (NST - 2)>();
+                __builtin_amdgcn_s_barrier();
+                load_frags(smem + (int)((kr + 1) % NST) * STAGE, 0, fr[0]);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+    }  // KS != 2
+    if constexpr (KS == 1) {
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < MI; ++ni) {
-                if constexpr (PAIR8) {
-                    mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
-                    mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
-                    mma_x8(acc[mi][ni], hi8_codes(f[0][mi], f[1][mi], cva), f[2][mi], f[5][ni],
-                           hi8_codes(f[3][ni], f[4][ni], cvb), sa8, sb8);
-                } else if constexpr (LS || RS) {
-                    mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
-                    if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
-                    if constexpr (LS) mma(acc[mi][ni], f[1][mi], f[NLP][ni], T{});
-                } else {
-                    mma(acc[mi][ni], f[0][mi], f[NLP][ni], T{});
-                }
-            }
-    };
-    // ds_read_b128 per K-unit; the counter holds 15 at most, and a wait for
-    // <= 15 outstanding is still enough when more were issued after the ones
-    // needed (in-order return)
-    constexpr int NDS = NFP * MI < 15 ? NFP * MI : 15;
-    Frag fr[2];
-    // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
-    // Every wave issues exactly NLD loads per iteration (the index is clamped
-    // at the end), so "tile kt+1 has landed" is vmcnt <= NLD * (NST - 2).
+            for (int ni = 0; ni < MI; ++ni)
 #pragma unroll
-    for (int t = 0; t < NST - 1; ++t) issue_loads(t < nk ? t : nk - 1, t);
-    wait_vmcnt<NLD * (NST - 2)>();
-    __builtin_amdgcn_s_barrier();
-    load_frags(smem, 0, fr[0]);
-    // Drain every LDS and scalar-memory access of the prologue, so that no
-    // scalar load (which may return out of order) is pending in the loop and
-    // the counted LDS waits below are the only ones needed.
-    wait_lgkmcnt<0>();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int st = (int)(kt % NST);
-        const uint8_t *base = smem + st * STAGE;
-        // stage (kt - 1) mod NST was last read in iteration kt - 1, which every
-        // wave finished before the barrier that ended it
-        const int64_t tn = kt + NST - 1;
-        issue_loads(tn < nk ? tn : nk - 1, (int)((kt + NST - 1) % NST));
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int sub = 0; sub < NSUB; ++sub) {
-            // next substep's fragments first, then this substep's MFMAs on
-            // fragments loaded one substep earlier: wait only for those (the
-            // NDS reads just issued may stay in flight under the MFMAs)
-            if (sub + 1 < NSUB) {
-                load_frags(base, sub + 1, fr[(sub + 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<NDS>();
-                mfmas(fr[sub & 1]);
-            } else if constexpr (PAIR8) {
-                // the unit's reads were issued in groups (substep 0, substep
-                // 1, codes): start on each group as it lands; every
-                // accumulator still sees substep 0, 1, then the cross terms
-                const Frag &f = fr[sub & 1];
-                __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<(4 * MI < 15 ? 4 * MI : 15)>();
-#pragma unroll
-                for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
-                __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<2 * MI>();
-#pragma unroll
-                for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
-                u32x4 ha[MI], hb[MI];
-#pragma unroll
-                for (int m = 0; m < MI; ++m) {
-                    ha[m] = hi8_codes(f[0][m], f[1][m], cva);
-                    hb[m] = hi8_codes(f[3][m], f[4][m], cvb);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<0>();
-#pragma unroll
-                for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < MI; ++ni) mma_x8(acc[mi][ni], ha[mi], f[2][mi], f[5][ni], hb[ni], sa8, sb8);
-            } else {
-                __builtin_amdgcn_sched_barrier(0);
-                wait_lgkmcnt<0>();
-                mfmas(fr[sub & 1]);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // Tile kt + 1 landed for this wave, then (barrier) for all waves. A
-        // plain s_barrier: a fenced __syncthreads would wait for every
-        // outstanding load (vmcnt(0)) and undo the prefetch. Every ds_read of
-        // the stage about to be refilled was consumed by an MFMA above.
-        wait_vmcnt<NLD * (NST - 2)>();
-        __builtin_amdgcn_s_barrier();
-        load_frags(smem + (int)((kt + 1) % NST) * STAGE, 0, fr[0]);
+                for (int q = 0; q < 4; ++q)
+                    *part_ptr(part, mi, ni, q) =
+                        f32x4{acc[mi][ni][4 * q], acc[mi][ni][4 * q + 1], acc[mi][ni][4 * q + 2], acc[mi][ni][4 * q + 3]};
+        return;
     }
-    __builtin_amdgcn_s_waitcnt(0);
 
     // ---------------- epilogue ----------------
     // Accumulator layout of a 32x32 MFMA block: lane l, register e holds
     // row 8 (e / 4) + 4 (l / 32) + (e % 4), column l % 32.
     const float acc_scale = ((LS || RS) && !X8) ? 1.0f / Elt<T>::kSplit : 1.0f;
+    const int mo = KS == 2 ? fmi : 0, no = KS == 2 ? fni : 0;  // block offsets of the fixup
     const bool diag = (bi == bj);
     if constexpr (EPI == EPI_FINAL) {
         if (dm.scal->nonfinite) return;  // leave the output untouched
@@ -455,13 +514,13 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const float hl = 0.5f * (float)dm.scal->lam * acc_scale;
         const int64_t n = dm.n;
 #pragma clang loop unroll(full)
-        for (int mi = 0; mi < MI; ++mi)
+        for (int mi = 0; mi < MIE; ++mi)
 #pragma clang loop unroll(full)
-            for (int ni = 0; ni < MI; ++ni)
+            for (int ni = 0; ni < MIE; ++ni)
 #pragma clang loop unroll(full)
                 for (int eg = 0; eg < 4; ++eg) {
-                    const int64_t ib = i0 + wr + mi * 32 + 8 * eg + 4 * (lane >> 5);
-                    const int64_t j = j0 + wc + ni * 32 + (lane & 31);
+                    const int64_t ib = i0 + wr + (mi + mo) * 32 + 8 * eg + 4 * (lane >> 5);
+                    const int64_t j = j0 + wc + (ni + no) * 32 + (lane & 31);
                     if (j >= n || ib >= n) continue;
 #pragma clang loop unroll(full)
                     for (int q = 0; q < 4; ++q) {
@@ -486,13 +545,13 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         uint8_t *Dx = (uint8_t *)dm.lo[g.sd];
         typedef T t4 __attribute__((ext_vector_type(4)));
 #pragma clang loop unroll(full)
-        for (int mi = 0; mi < MI; ++mi)
+        for (int mi = 0; mi < MIE; ++mi)
 #pragma clang loop unroll(full)
-            for (int ni = 0; ni < MI; ++ni)
+            for (int ni = 0; ni < MIE; ++ni)
 #pragma clang loop unroll(full)
                 for (int eg = 0; eg < 4; ++eg) {
-                    const int64_t ib = i0 + wr + mi * 32 + 8 * eg + 4 * (lane >> 5);
-                    const int64_t j = j0 + wc + ni * 32 + (lane & 31);
+                    const int64_t ib = i0 + wr + (mi + mo) * 32 + 8 * eg + 4 * (lane >> 5);
+                    const int64_t j = j0 + wc + (ni + no) * 32 + (lane & 31);
                     float v[4];
 #pragma clang loop unroll(full)
                     for (int q = 0; q < 4; ++q) v[q] = g.beta * (acc[mi][ni][4 * eg + q] * acc_scale);
@@ -632,29 +691,60 @@ int64_t gemm_padded_size(int64_t n, bool big) {
 
 int gemm_tile_generation() { return g_tile_gen; }
 
-// The 256 tile runs one workgroup per CU, so a list of B such tiles takes
-// ceil(B / CUs) rounds and a partial last round idles most of the chip
-// (measured: ~1000 TFLOP/s just under a whole number of rounds, ~860 just
-// over). The last B mod CUs tiles therefore run as 128 tiles (two workgroups
-// per CU, a quarter of the work each) in the product's second launch.
+// The 256 tile runs one workgroup per CU, so B such tiles take ceil(B / CUs)
+// rounds and a partial last round idles most of the chip (measured: ~1000
+// TFLOP/s just under a whole number of rounds, ~860 just over). A matrix's
+// last B mod CUs tiles therefore run apart from its whole rounds: when they
+// fill at most half the CUs, each is cut into c = min(CUs / tail, 8) K-chunks
+// (one 256-tile workgroup each, FP32 partials) and a fixup sums the chunks in
+// order; otherwise each runs as four 128 tiles (two workgroups per CU) in the
+// product's last launch. The rule is per matrix, so a matrix's result does
+// not depend on the other matrices of a batch.
+static int g_ksplit_max = 8;  // tuning hook: most K-chunks per tile (1: never split)
+
 void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out) {
     out.big.clear();
     out.small_plain.clear();
     out.small_all.clear();
+    out.split.clear();
+    out.fixup.clear();
+    out.parts = 0;
+    int max_chunks = 0;
     for (size_t m = 0; m < np.size(); ++m) {
-        if (big[m]) append_tile_order(out.big, (uint32_t)m, (int)(np[m] / 256));
-        else append_tile_order(out.small_plain, (uint32_t)m, (int)(np[m] / 128));
-        append_tile_order(out.small_all, (uint32_t)m, (int)(np[m] / 128));
+        append_tile_order(out.small_all, (uint32_t)m, (int)(np[m] / kTile));
+        if (!big[m]) {
+            append_tile_order(out.small_plain, (uint32_t)m, (int)(np[m] / kTile));
+            continue;
+        }
+        std::vector<WorkItem> t;
+        append_tile_order(t, (uint32_t)m, (int)(np[m] / kTile2));
+        const size_t tail = (g_tile_override == kTile2 || cus <= 0) ? 0 : t.size() % (size_t)cus;
+        const int chunks = tail ? std::min<int>((int)((size_t)cus / tail), g_ksplit_max) : 0;
+        out.big.insert(out.big.end(), t.begin(), t.end() - tail);
+        for (size_t k = t.size() - tail; k < t.size(); ++k) {
+            const WorkItem w = t[k];
+            if (chunks >= 2) {
+                out.fixup.push_back(uint4{w.x, w.y, (uint32_t)chunks << 8, (uint32_t)out.parts});
+                out.parts += chunks;
+                max_chunks = std::max(max_chunks, chunks);
+                continue;
+            }
+            const uint32_t bi = w.y & 0xFFFFu, bj = w.y >> 16;
+            for (uint32_t sj = 2 * bj; sj < 2 * bj + 2; ++sj)
+                for (uint32_t si = 2 * bi; si < 2 * bi + 2; ++si)
+                    if (si <= sj) out.small_plain.push_back(WorkItem{w.x, si | (sj << 16)});
+        }
     }
-    const size_t tail = (g_tile_override == 256 || cus <= 0) ? 0 : out.big.size() % (size_t)cus;
-    for (size_t k = out.big.size() - tail; k < out.big.size(); ++k) {
-        const WorkItem w = out.big[k];
-        const uint32_t bi = w.y & 0xFFFFu, bj = w.y >> 16;
-        for (uint32_t sj = 2 * bj; sj < 2 * bj + 2; ++sj)
-            for (uint32_t si = 2 * bi; si < 2 * bi + 2; ++si)
-                if (si <= sj) out.small_plain.push_back(WorkItem{w.x, si | (sj << 16)});
-    }
-    out.big.resize(out.big.size() - tail);
+    // chunk-major: the workgroups of one chunk index are consecutive, so the
+    // tiles an XCD runs together read the same K range
+    for (int c = 0; c < max_chunks; ++c)
+        for (const uint4 &f : out.fixup)
+            if ((int)(f.z >> 8) > c) out.split.push_back(uint4{f.x, f.y, (uint32_t)c | f.z, f.w + (uint32_t)c});
+}
+
+void gemm_set_ksplit_max(int c) {
+    g_ksplit_max = c;
+    ++g_tile_gen;
 }
 
 // LDS configuration per (tile, operand panels). The 128 tile keeps two
@@ -676,76 +766,91 @@ template <int BM, int NP> struct LdsCfg {
 };
 
 template <typename T, bool LS, bool RS, int EPI, int BM, bool X8 = false>
-static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s) {
+static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s, int ks) {
     constexpr int NP = 2 + (LS ? 1 : 0) + (RS ? 1 : 0);
     constexpr int ROWB = LdsCfg<BM, NP>::ROWB;
     constexpr int NST = LdsCfg<BM, NP>::NST;
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST, X8>), dim3((unsigned)ntiles), dim3(kThreads), 0,
-                       s, g);
+    const dim3 grid((unsigned)ntiles), blk(kThreads);
+    if (ks == 0) {
+        hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST, X8, 0>), grid, blk, 0, s, g);
+    } else if constexpr (BM == kTile2 && sizeof(T) == 2) {
+        if (!g.split || !g.part) return hipErrorInvalidValue;
+        // the chunks have no epilogue: one instantiation serves every EPI
+        if (ks == 1)
+            hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI_STORE, BM, ROWB, NST, X8, 1>), grid, blk, 0, s, g);
+        else if (ks == 2)  // (BM / 64)^2 workgroups per fixup entry
+            hipLaunchKernelGGL((gemm_sym_kernel<T, LS, RS, EPI, BM, ROWB, NST, X8, 2>),
+                               dim3((unsigned)(ntiles * (BM / 64) * (BM / 64))), blk, 0, s, g);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <int EPI>
-static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s) {
+static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s, int ks) {
     if (pair) {
         switch (bm) {
-            case 256: return launch_bm<f16, true, true, EPI, 256, true>(g, ntiles, s);
-            case 128: return launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s);
+            case 256: return launch_bm<f16, true, true, EPI, 256, true>(g, ntiles, s, ks);
+            case 128: return launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s, ks);
         }
         return hipErrorInvalidValue;
     }
     switch (bm) {
-        case 256: return launch_bm<f16, false, false, EPI, 256, true>(g, ntiles, s);
-        case 128: return launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s);
+        case 256: return launch_bm<f16, false, false, EPI, 256, true>(g, ntiles, s, ks);
+        case 128: return launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s, ks);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T, bool LS, bool RS, int EPI>
-static hipError_t launch_t(const GemmArgs &g, int bm, int64_t ntiles, hipStream_t s) {
+static hipError_t launch_t(const GemmArgs &g, int bm, int64_t ntiles, hipStream_t s, int ks) {
     switch (bm) {
-        case 256: return launch_bm<T, LS, RS, EPI, 256>(g, ntiles, s);
-        case 128: return launch_bm<T, LS, RS, EPI, 128>(g, ntiles, s);
+        case 256: return launch_bm<T, LS, RS, EPI, 256>(g, ntiles, s, ks);
+        case 128: return launch_bm<T, LS, RS, EPI, 128>(g, ntiles, s, ks);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T, int EPI>
-static hipError_t launch_split(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s) {
-    if (ls && rs) return launch_t<T, true, true, EPI>(g, bm, ntiles, s);
-    if (ls) return launch_t<T, true, false, EPI>(g, bm, ntiles, s);
-    if (rs) return launch_t<T, false, true, EPI>(g, bm, ntiles, s);
-    return launch_t<T, false, false, EPI>(g, bm, ntiles, s);
+static hipError_t launch_split(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s, int ks) {
+    if (ls && rs) return launch_t<T, true, true, EPI>(g, bm, ntiles, s, ks);
+    if (ls) return launch_t<T, true, false, EPI>(g, bm, ntiles, s, ks);
+    if (rs) return launch_t<T, false, true, EPI>(g, bm, ntiles, s, ks);
+    return launch_t<T, false, false, EPI>(g, bm, ntiles, s, ks);
 }
 
 template <typename T>
-static hipError_t launch_epi(const GemmArgs &g, int epi, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s) {
+static hipError_t launch_epi(const GemmArgs &g, int epi, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s,
+                             int ks) {
     switch (epi) {
-        case EPI_STORE: return launch_split<T, EPI_STORE>(g, ls, rs, bm, ntiles, s);
-        case EPI_STORE_SPLIT: return launch_split<T, EPI_STORE_SPLIT>(g, ls, rs, bm, ntiles, s);
-        case EPI_FINAL: return launch_split<T, EPI_FINAL>(g, ls, rs, bm, ntiles, s);
+        case EPI_STORE: return launch_split<T, EPI_STORE>(g, ls, rs, bm, ntiles, s, ks);
+        case EPI_STORE_SPLIT: return launch_split<T, EPI_STORE_SPLIT>(g, ls, rs, bm, ntiles, s, ks);
+        case EPI_FINAL: return launch_split<T, EPI_FINAL>(g, ls, rs, bm, ntiles, s, ks);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool rs, int bm, int64_t ntiles,
-                           hipStream_t s) {
+                           hipStream_t s, int ks) {
     switch (dtype) {
         case DT_F32:
-            if (ls || rs || epi == EPI_STORE_SPLIT) return hipErrorInvalidValue;
-            return epi == EPI_STORE ? launch_t<float, false, false, EPI_STORE>(g, bm, ntiles, s)
-                                    : launch_t<float, false, false, EPI_FINAL>(g, bm, ntiles, s);
-        case DT_F16: return launch_epi<f16>(g, epi, ls, rs, bm, ntiles, s);
+            if (ls || rs || epi == EPI_STORE_SPLIT || ks) return hipErrorInvalidValue;
+            return epi == EPI_STORE ? launch_t<float, false, false, EPI_STORE>(g, bm, ntiles, s, 0)
+                                    : launch_t<float, false, false, EPI_FINAL>(g, bm, ntiles, s, 0);
+        case DT_F16: return launch_epi<f16>(g, epi, ls, rs, bm, ntiles, s, ks);
         case DT_F16X8:
             if (ls != rs) return hipErrorInvalidValue;
             switch (epi) {
-                case EPI_STORE: return launch_x8<EPI_STORE>(g, ls, bm, ntiles, s);
-                case EPI_STORE_SPLIT: return launch_x8<EPI_STORE_SPLIT>(g, ls, bm, ntiles, s);
-                case EPI_FINAL: return launch_x8<EPI_FINAL>(g, ls, bm, ntiles, s);
+                case EPI_STORE: return launch_x8<EPI_STORE>(g, ls, bm, ntiles, s, ks);
+                case EPI_STORE_SPLIT: return launch_x8<EPI_STORE_SPLIT>(g, ls, bm, ntiles, s, ks);
+                case EPI_FINAL: return launch_x8<EPI_FINAL>(g, ls, bm, ntiles, s, ks);
             }
             return hipErrorInvalidValue;
-        case DT_BF16: return launch_epi<bf16>(g, epi, ls, rs, bm, ntiles, s);
+        case DT_BF16: return launch_epi<bf16>(g, epi, ls, rs, bm, ntiles, s, ks);
     }
     return hipErrorInvalidValue;
 }

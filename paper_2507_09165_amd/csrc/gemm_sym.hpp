@@ -13,6 +13,9 @@ enum Epi { EPI_STORE = 0, EPI_STORE_SPLIT = 1, EPI_FINAL = 2 };
 
 // Output tile edge; work matrices are zero-padded to a multiple of it.
 constexpr int kTile = 128;
+// The large tile edge, and the bytes of one FP32 partial tile of a K-split.
+constexpr int kTile2 = 256;
+constexpr size_t kPartBytes = sizeof(float) * kTile2 * kTile2;
 
 // One symmetric product D = alpha C0 + beta (L R) + gamma I for every matrix
 // named by the tile list. Operands, addend and output are work slots of the
@@ -27,12 +30,18 @@ struct GemmArgs {
     int c0_split;
     float alpha, beta, gamma;
     int es_l, es_r, es_c0, es_d;  // FP8-pair code exponents of the slots (DT_F16X8)
+    // K-split tiles (ks = 1: chunk list, ks = 2: fixup list; see TileLists)
+    // and their FP32 partial tiles (kTile2 x kTile2 floats each)
+    const uint4 *split;
+    float *part;
 };
 
 // ls / rs: L / R carry lo halves. bm: tile edge (128 or 256; it must divide
-// every listed matrix's np). ntiles: length of the tile list.
+// every listed matrix's np). ntiles: length of the tile list. ks: 0 = whole
+// tiles from g.tiles; 1 = K-chunks of split tiles, 2 = their fixup, both from
+// g.split and for bm = 256 only.
 hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool rs, int bm, int64_t ntiles,
-                           hipStream_t s);
+                           hipStream_t s, int ks = 0);
 // Append matrix m's upper tiles (T x T tile grid) in the blocked schedule order.
 void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T);
 
@@ -47,8 +56,14 @@ int64_t gemm_padded_size(int64_t n, bool big);
 // one workgroup per CU), `small_plain` (the rest of the plain products as 128
 // tiles), `small_all` (every matrix's full triangle of 128 tiles, for split
 // products). np: padded orders; big: gemm_use_big per matrix; cus: CU count.
+// `split` / `fixup` (uint4 entries, see gemm_sym_kernel's KS): the matrices
+// whose last partial round of 256 tiles is at most half the CUs run those
+// tiles as K-chunks (one workgroup each, chunks = CUs / tail tiles, at most
+// 8) plus a fixup per tile; `parts` partial tiles in all.
 struct TileLists {
     std::vector<WorkItem> big, small_plain, small_all;
+    std::vector<uint4> split, fixup;
+    int64_t parts = 0;
 };
 void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out);
 // Incremented whenever a tuning hook changes the tile choice.
@@ -63,6 +78,8 @@ void gemm_set_big_tiles(int64_t min_n, int tail_cus);
 // FP8 pairs.
 bool gemm_split_big(int dtype);
 void gemm_set_split_big(int mask);
+// Tuning hook: most K-chunks a tail tile is cut into (1: never).
+void gemm_set_ksplit_max(int c);
 // Tuning hook: force the tile edge (0 restores the automatic choice).
 void gemm_set_tile_override(int bm);
 // Tuning hook: blocking of the tile schedule (H tile rows x W tile columns).

@@ -165,10 +165,13 @@ struct Plan {
     std::vector<int64_t> ns;
     // layout
     StagePlan sp;
-    // GEMM work lists: [0] 256 tiles of plain products, [1] 128 tiles of plain
-    // products, [2] 128 tiles of split products (gemm_tile_lists)
+    // GEMM work lists (gemm_tile_lists): [0] whole rounds of 256 tiles, [1]
+    // 128 tiles (small matrices, unsplit tails), [2] 128 tiles of every
+    // matrix (split products without the 256 tile); K-chunks and fixups of
+    // the split tail tiles, and their partial tiles
     size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[3] = {0, 0, 0}, total = 0;
-    int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[3] = {0, 0, 0};
+    size_t off_split = 0, off_fixup = 0, off_part = 0;
+    int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[3] = {0, 0, 0}, n_split = 0, n_fixup = 0;
     int gemm_bm[3] = {256, 128, 128};
     TileLists tiles;
     int cus = 256;       // compute units the tail split is sized for
@@ -213,6 +216,8 @@ void layout_plan(Plan &P) {
     P.n_gemm[0] = (int64_t)P.tiles.big.size();
     P.n_gemm[1] = (int64_t)P.tiles.small_plain.size();
     P.n_gemm[2] = (int64_t)P.tiles.small_all.size();
+    P.n_split = (int64_t)P.tiles.split.size();
+    P.n_fixup = (int64_t)P.tiles.fixup.size();
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     P.off_desc = take(sizeof(MatDesc) * M);
@@ -221,6 +226,9 @@ void layout_plan(Plan &P) {
     P.off_wsymv = take(sizeof(WorkItem) * (size_t)P.n_symv);
     P.off_wcast = take(sizeof(WorkItem) * (size_t)P.n_cast);
     for (int c = 0; c < 3; ++c) P.off_wgemm[c] = take(sizeof(WorkItem) * (size_t)P.n_gemm[c]);
+    P.off_split = take(sizeof(uint4) * (size_t)P.n_split);
+    P.off_fixup = take(sizeof(uint4) * (size_t)P.n_fixup);
+    P.off_part = take(kPartBytes * (size_t)P.tiles.parts);
     for (const MatLayout &L : P.mats) P.mat_off.push_back(take(L.total));
     P.total = off;
 }
@@ -262,7 +270,9 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         !up(P.off_wcast, wc.data(), sizeof(WorkItem) * wc.size()) ||
         !up(P.off_wgemm[0], wg[0]->data(), sizeof(WorkItem) * wg[0]->size()) ||
         !up(P.off_wgemm[1], wg[1]->data(), sizeof(WorkItem) * wg[1]->size()) ||
-        !up(P.off_wgemm[2], wg[2]->data(), sizeof(WorkItem) * wg[2]->size()))
+        !up(P.off_wgemm[2], wg[2]->data(), sizeof(WorkItem) * wg[2]->size()) ||
+        !up(P.off_split, P.tiles.split.data(), sizeof(uint4) * P.tiles.split.size()) ||
+        !up(P.off_fixup, P.tiles.fixup.data(), sizeof(uint4) * P.tiles.fixup.size()))
         return PSDPROJ_ERR_HIP;
     P.base = base;
     return PSDPROJ_OK;
@@ -388,6 +398,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
 
     GemmArgs g{};
     g.D = B.desc;
+    g.part = (float *)(b + P.off_part);
     g.io_tab = B.io_tab;
     g.io0 = B.io0;
     // one product over every matrix, one launch per tile class
@@ -402,15 +413,26 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         if (g_timer.on && (rec.a = g_timer.take()) && (rec.b = g_timer.take())) {
             if (hipEventRecord(rec.a, s) != hipSuccess) return hipErrorUnknown;
         }
-        // the 256-tile rounds, then the 128 tiles; split products without
-        // the 256 tile: the list of 128 tiles only
-        const bool small = (ls || rs) && !P.split_big;
-        for (int c = small ? 2 : 0; c < (small ? 3 : 2); ++c) {
-            if (!P.n_gemm[c]) continue;
+        // the 256-tile rounds, the K-chunks of the tail tiles and their
+        // fixup, then the 128 tiles; split products without the 256 tile: the
+        // list of 128 tiles only
+        auto launch = [&](int c, int ks) -> hipError_t {
+            const int64_t cnt = ks == 0 ? P.n_gemm[c] : (ks == 1 ? P.n_split : P.n_fixup);
+            if (!cnt) return hipSuccess;
             g.tiles = (const WorkItem *)(b + P.off_wgemm[c]);
-            const hipError_t r = gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], P.n_gemm[c], s);
-            if (r != hipSuccess) return r;
+            g.split = (const uint4 *)(b + (ks == 1 ? P.off_split : P.off_fixup));
+            return gemm_sym_launch(g, p.dtype, epi, ls, rs, P.gemm_bm[c], cnt, s, ks);
+        };
+        hipError_t r = hipSuccess;
+        if ((ls || rs) && !P.split_big) {
+            r = launch(2, 0);
+        } else {
+            r = launch(0, 0);
+            if (r == hipSuccess) r = launch(0, 1);
+            if (r == hipSuccess) r = launch(0, 2);
+            if (r == hipSuccess) r = launch(1, 0);
         }
+        if (r != hipSuccess) return r;
         if (epi != EPI_FINAL) slot_e[sd] = e_out;
         if (rec.b) {
             if (hipEventRecord(rec.b, s) != hipSuccess) return hipErrorUnknown;
@@ -742,6 +764,11 @@ int psdproj_tune(const char *key, int64_t value) {
     if (!strcmp(key, "gemm_split_big")) {  // bit 0: FP16/BF16 pairs, bit 1: FP8 pairs on 256 tiles
         if (value < 0 || value > 3) return PSDPROJ_ERR_INVALID_ARG;
         gemm_set_split_big((int)value);
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "gemm_ksplit")) {  // most K-chunks of a tail tile (1: never split)
+        if (value < 1 || value > 64) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_ksplit_max((int)value);
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_block")) {  // value = H * 256 + W

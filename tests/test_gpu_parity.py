@@ -237,3 +237,57 @@ def test_mixed_tile_sizes_bitwise_equal(mode):
     info = P.read_info(info_t)
     ref, _ = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"])
     assert rel_fro(mix_t.cpu().numpy(), ref) <= TOL_POLY[mode]
+
+
+def _with_tuning(settings, fn):
+    try:
+        for k, v in settings:
+            P.tune(k, v)
+        return fn()
+    finally:
+        P.tune("gemm_ksplit", 8)
+        P.tune("gemm_tail_cus", 0)
+        P.tune("gemm_big_min", 6144)
+        P.tune("gemm_tile", 0)
+
+
+@pytest.mark.parametrize("mode", ["fp16", "fp8_fp16_split"])
+def test_ksplit_tail_tiles(mode):
+    """Tail tiles cut into K-chunks (forced: 256 tiles from n = 512 and a tail
+    rule for 64 CUs, so all 21 tiles of n = 1500 form the tail, 3 chunks
+    each): deterministic, equal to 128 tiles up to rounding, matches the
+    oracle, and a batch holding the matrix gives it the same bits."""
+    import torch
+    X32 = inputs.goe(1500, 22)
+    Xg = to_dev(X32)
+    Xs = to_dev(inputs.goe(700, 23))
+    say("ksplit tail", mode)
+    ref_t, info_t = _with_tuning([("gemm_tile", 128)], lambda: P.project_ex(Xg, mode=mode))
+    forced = [("gemm_big_min", 512), ("gemm_tail_cus", 64)]
+    a = _with_tuning(forced, lambda: P.project(Xg, mode=mode))
+    b = _with_tuning(forced, lambda: P.project(Xg, mode=mode))
+    batch = _with_tuning(forced, lambda: P.project_batched([Xs, Xg], mode=mode))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(batch[1], a)
+    assert not torch.isnan(a).any()
+    info = P.read_info(info_t)
+    ref, _ = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"])
+    out = a.cpu().numpy()
+    assert rel_fro(out, ref) <= TOL_POLY[mode]
+    assert rel_fro(out, ref_t.cpu().numpy()) <= TOL_POLY[mode]
+
+
+def test_ksplit_more_chunks_than_k_tiles():
+    """A 512 x 512 work matrix (3 tiles of 256, all in the tail) cut into 21
+    K-chunks, more than its 8 K-tiles: the empty chunks add zero partials."""
+    import torch
+    X32 = inputs.goe(500, 24)
+    Xg = to_dev(X32)
+    say("ksplit empty chunks")
+    settings = [("gemm_big_min", 256), ("gemm_tail_cus", 64), ("gemm_ksplit", 64)]
+    out_t, info_t = _with_tuning(settings, lambda: P.project_ex(Xg, mode="fp8_fp16_split"))
+    torch.cuda.synchronize()
+    info = P.read_info(info_t)
+    ref, _ = oracle.project_poly(X32.astype(np.float64), "fp8_fp16_split", lam=info["lambda"])
+    assert rel_fro(out_t.cpu().numpy(), ref) <= TOL_POLY["fp8_fp16_split"]
