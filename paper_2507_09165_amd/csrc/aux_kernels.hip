@@ -252,47 +252,100 @@ __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const 
     }
 }
 
-// y_k from the symv tile partials (fixed order: column dots of tiles I <= K,
-// then row sums of tiles J >= K). NORMS: also colsq_k. ORTH0: also the first
+// The small vector kernels of a Lanczos step run 4 groups of kRows threads
+// per block of kRows rows, so that four times as many loads are in flight.
+constexpr int kGroups = 4;
+constexpr int kVecThreads = kGroups * kRows;
+constexpr int kColsPerGroup = kMaxLanczos / kGroups;  // Lanczos columns c = kGroups m + g
+
+// Per-group block sums of NV doubles per thread over the group's kRows rows:
+// each wave sums its 64 rows, then the group's waves are added in order
+// (the same order for every group, and the order of block_reduce). Row sums
+// of column v of group g land in out[g][v] (LDS, valid after the call).
+template <int NV>
+__device__ __forceinline__ void group_reduce(double (&v)[NV], double *sh /* [16][NV] */,
+                                             double (*out)[NV] /* [kGroups][NV] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < kGroups * NV) {
+        const int g = threadIdx.x / NV, k = threadIdx.x % NV;
+        const double *w = sh + 4 * g * NV + k;
+        out[g][k] = w[0] + w[NV] + w[2 * NV] + w[3 * NV];
+    }
+    __syncthreads();
+}
+
+// y_k from the symv tile partials. Its T + 1 terms (column dots of tiles
+// I = 0..K, then row sums of tiles J = K..T-1) are cut into four consecutive
+// runs, one per thread group, each summed in order; the four run sums are
+// added in group order. NORMS: also colsq_k. ORTH0: also the first
 // Gram-Schmidt partials pa[block][c] = sum over this block's rows of
 // V[i, c] y_i, c <= jstep.
 template <bool NORMS, bool ORTH0>
-__global__ __launch_bounds__(256) void symv_reduce_kernel(const MatDesc *D, const WorkItem *W, int dst, int jstep,
-                                                          int stop_on_flag) {
+__global__ __launch_bounds__(kVecThreads) void symv_reduce_kernel(const MatDesc *D, const WorkItem *W, int dst,
+                                                                  int jstep, int stop_on_flag) {
     const WorkItem wi = W[blockIdx.x];
     const MatDesc &dm = D[wi.x];
     if (stop_on_flag && dm.scal->stop) return;
     const int64_t n = dm.n;
     const int b = (int)wi.y;
-    const int64_t k = (int64_t)b * kRows + threadIdx.x;
+    const int r = threadIdx.x % kRows, g = threadIdx.x / kRows;
+    const int64_t k = (int64_t)b * kRows + r;
     const int T = (int)((n + kTB - 1) / kTB);
     double *y = dst == DST_U ? dm.u : (dst == DST_W ? dm.w : dm.w2);
-    double yk = 0.0, ck = 0.0;
+    __shared__ double ry[kGroups][kRows], rc[NORMS ? kGroups : 1][kRows];
+    __shared__ double yb[kRows];
+    double ys = 0.0, cs = 0.0;
     if (k < n) {
         const int K = (int)(k / kTB), kk = (int)(k % kTB);
         const int64_t base = (int64_t)K * (K + 1) / 2;
+        const int nt = T + 1, q = (nt + kGroups - 1) / kGroups;
+        const int t0 = g * q < nt ? g * q : nt, t1 = t0 + q < nt ? t0 + q : nt;
+        // terms t <= K: column dots of tile (t, K); t > K: row sums of tile (K, t - 1)
+        const int d1 = t1 < K + 1 ? t1 : K + 1;
 #pragma unroll 8
-        for (int I = 0; I <= K; ++I) {
-            yk += dm.sd[(base + I) * kTB + kk];
-            if constexpr (NORMS) ck += dm.sd2[(base + I) * kTB + kk];
+        for (int t = t0; t < d1; ++t) {
+            ys += dm.sd[(base + t) * kTB + kk];
+            if constexpr (NORMS) cs += dm.sd2[(base + t) * kTB + kk];
         }
 #pragma unroll 8
-        for (int J = K; J < T; ++J) {
-            const int64_t t = (int64_t)J * (J + 1) / 2 + K;
-            yk += dm.sa[t * kTB + kk];
-            if constexpr (NORMS) ck += dm.sa2[t * kTB + kk];
+        for (int t = (t0 > K + 1 ? t0 : K + 1); t < t1; ++t) {
+            const int64_t tl = (int64_t)(t - 1) * t / 2 + K;
+            ys += dm.sa[tl * kTB + kk];
+            if constexpr (NORMS) cs += dm.sa2[tl * kTB + kk];
         }
-        y[k] = yk;
-        if constexpr (NORMS) dm.colsq[k] = ck;
+    }
+    ry[g][r] = ys;
+    if constexpr (NORMS) rc[g][r] = cs;
+    __syncthreads();
+    if (g == 0) {
+        const double yk = ((ry[0][r] + ry[1][r]) + ry[2][r]) + ry[3][r];
+        if (k < n) {
+            y[k] = yk;
+            if constexpr (NORMS) dm.colsq[k] = ((rc[0][r] + rc[1][r]) + rc[2][r]) + rc[3][r];
+        }
+        yb[r] = k < n ? yk : 0.0;
     }
     if constexpr (ORTH0) {
-        __shared__ double red[4 * kMaxLanczos];
-        double h[kMaxLanczos];
+        __shared__ double sh[16 * kColsPerGroup];
+        __shared__ double hs[kGroups][kColsPerGroup];
+        __syncthreads();
+        double h[kColsPerGroup];
 #pragma unroll
-        for (int c = 0; c < kMaxLanczos; ++c) h[c] = (c <= jstep && k < n) ? dm.V[(int64_t)c * n + k] * yk : 0.0;
-        block_reduce<kMaxLanczos>(h, red);
-        if (threadIdx.x == 0)
-            for (int c = 0; c <= jstep; ++c) dm.pa[(int64_t)b * kMaxLanczos + c] = h[c];
+        for (int m = 0; m < kColsPerGroup; ++m) {
+            const int c = kGroups * m + g;
+            h[m] = (c <= jstep && k < n) ? dm.V[(int64_t)c * n + k] * yb[r] : 0.0;
+        }
+        group_reduce<kColsPerGroup>(h, sh, hs);
+        if (threadIdx.x <= jstep) {
+            const int c = threadIdx.x;
+            dm.pa[(int64_t)b * kMaxLanczos + c] = hs[c % kGroups][c / kGroups];
+        }
     }
 }
 
@@ -329,43 +382,63 @@ __global__ __launch_bounds__(256) void lz_start_kernel(const MatDesc *D, const W
 // Orthogonalisation pass of step j over the rows of this block.
 //  pass 1: h = sum(pa); alpha_j = h_j; w -= V h; pb <- V^T w (second GS pass)
 //  pass 2: h = sum(pb); w -= V h; pa <- ||w||^2
-// (the first pass's partials come with the reduction that formed w)
-__global__ __launch_bounds__(256) void lz_orth_kernel(const MatDesc *D, const WorkItem *W, int j, int pass) {
+// (the first pass's partials come with the reduction that formed w). Thread
+// group g holds the columns c = 4 m + g of V for its row: (V h)_i is the sum
+// of the four groups' sums, added in group order.
+__global__ __launch_bounds__(kVecThreads) void lz_orth_kernel(const MatDesc *D, const WorkItem *W, int j, int pass) {
     const WorkItem wi = W[blockIdx.x];
     const MatDesc &dm = D[wi.x];
     Scalars *scal = dm.scal;
     if (scal->stop) return;
     const int b = (int)wi.y;
-    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
+    const int r = threadIdx.x % kRows, g = threadIdx.x / kRows;
+    const int64_t i = (int64_t)b * kRows + r, n = dm.n;
     const double *part_in = pass == 1 ? dm.pa : dm.pb;
     double *part_out = pass == 1 ? dm.pb : dm.pa;
     __shared__ double hsh[kMaxLanczos];
-    __shared__ double red[4 * kMaxLanczos];
-    double wi_ = (i < n) ? dm.w[i] : 0.0;
+    __shared__ double rs[kGroups][kRows];
+    __shared__ double wb[kRows];
+    __shared__ double sh[16 * kColsPerGroup];
+    __shared__ double hs[kGroups][kColsPerGroup];
     if (threadIdx.x <= j) hsh[threadIdx.x] = sum_partials(part_in, dm.nbv, kMaxLanczos, threadIdx.x);
+    double v[kColsPerGroup];
+#pragma unroll
+    for (int m = 0; m < kColsPerGroup; ++m) {
+        const int c = kGroups * m + g;
+        v[m] = (c <= j && i < n) ? dm.V[(int64_t)c * n + i] : 0.0;
+    }
     __syncthreads();
     if (pass == 1 && b == 0 && threadIdx.x == 0) {
         scal->alpha[j] = hsh[j];
         scal->amax = fmax(scal->amax, fabs(hsh[j]));
     }
-    if (i < n) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = 0; k <= j; ++k) s += dm.V[(int64_t)k * n + i] * hsh[k];
-        wi_ -= s;
-        dm.w[i] = wi_;
-    }
-    if (pass == 1) {
-        double h[kMaxLanczos];
+    double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMaxLanczos; ++k) h[k] = (k <= j && i < n) ? dm.V[(int64_t)k * n + i] * wi_ : 0.0;
-        block_reduce<kMaxLanczos>(h, red);
-        if (threadIdx.x == 0)
-            for (int k = 0; k <= j; ++k) part_out[(int64_t)b * kMaxLanczos + k] = h[k];
+    for (int m = 0; m < kColsPerGroup; ++m) {
+        const int c = kGroups * m + g;
+        if (c <= j) s += v[m] * hsh[c];
+    }
+    rs[g][r] = s;
+    __syncthreads();
+    if (g == 0) {
+        double w_i = 0.0;
+        if (i < n) {
+            w_i = dm.w[i] - (((rs[0][r] + rs[1][r]) + rs[2][r]) + rs[3][r]);
+            dm.w[i] = w_i;
+        }
+        wb[r] = w_i;
+    }
+    __syncthreads();
+    if (pass == 1) {
+        double h[kColsPerGroup];
+#pragma unroll
+        for (int m = 0; m < kColsPerGroup; ++m) h[m] = v[m] * wb[r];
+        group_reduce<kColsPerGroup>(h, sh, hs);
+        if (threadIdx.x <= j) part_out[(int64_t)b * kMaxLanczos + threadIdx.x] = hs[threadIdx.x % kGroups][threadIdx.x / kGroups];
     } else {
-        double x[1] = {wi_ * wi_};
-        block_reduce<1>(x, red);
-        if (threadIdx.x == 0) part_out[(int64_t)b * kMaxLanczos] = x[0];
+        double x[1] = {wb[r] * wb[r]};
+        group_reduce<1>(x, sh, (double(*)[1])hs);
+        if (threadIdx.x == 0) part_out[(int64_t)b * kMaxLanczos] = hs[0][0];
     }
 }
 
@@ -629,13 +702,13 @@ hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int fo
             hipLaunchKernelGGL(symv_tile_kernel<false>, dim3(nt), dim3(256), 0, s, D, Wt, B.io_tab, B.io0, src, jstep,
                                stop_flag);
         if (norms)
-            hipLaunchKernelGGL((symv_reduce_kernel<true, false>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+            hipLaunchKernelGGL((symv_reduce_kernel<true, false>), dim3(nv), dim3(kVecThreads), 0, s, D, Wv, dst, jstep,
                                stop_flag);
         else if (orth0)
-            hipLaunchKernelGGL((symv_reduce_kernel<false, true>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+            hipLaunchKernelGGL((symv_reduce_kernel<false, true>), dim3(nv), dim3(kVecThreads), 0, s, D, Wv, dst, jstep,
                                stop_flag);
         else
-            hipLaunchKernelGGL((symv_reduce_kernel<false, false>), dim3(nv), dim3(256), 0, s, D, Wv, dst, jstep,
+            hipLaunchKernelGGL((symv_reduce_kernel<false, false>), dim3(nv), dim3(kVecThreads), 0, s, D, Wv, dst, jstep,
                                stop_flag);
     };
     hipLaunchKernelGGL(scal_init_kernel, dim3(M), dim3(64), 0, s, D);
@@ -644,8 +717,8 @@ hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int fo
     for (int j = 0; j < steps; ++j) {
         symv(SRC_V, j, DST_U, j == 0, false, 1);  // u = X v_j (first step: + column norms)
         symv(SRC_U, j, DST_W, false, true, 1);    // w = X u, pa = V^T w
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, 1);
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, 2);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 1);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 2);
         hipLaunchKernelGGL(lz_next_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, steps);
     }
     if (steps <= 20)
