@@ -122,7 +122,8 @@ def gemm_roofline(X, out, opts, n, mode, stream):
         v["tflops_per_product_equivalent"] = flops / (v["avg_ms"] * 1e-3) / 1e12
     tr = measured_traffic(mode) if n == 10000 else None
     res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection products; from n = 6144 one "
-                     "product is a launch of 256 x 256 tiles over whole rounds plus a launch of the 128 x 128 tail)",
+                     "product is a launch of 256 x 256 tiles over whole rounds, a launch of the last round's "
+                     "tiles cut into K-chunks, and their fixup)",
            "bound": "mfma",
            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
            "traffic": tr["traffic_bytes_per_launch"] if tr else None, "ms_per_launch": ms, "flops_per_launch": flops,
