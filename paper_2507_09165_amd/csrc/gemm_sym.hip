@@ -271,16 +271,16 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     // also waits for the next substep's reads; as asm, the reads get counted
     // waits. Completion of the DMA is awaited explicitly (vmcnt + barrier
     // below), as before.
+    auto issue_one = [&](int64_t kt, int buf, int j) {
+        const uint32_t la = (uint32_t)(uintptr_t)(smem + buf * STAGE + (wave_u * NLD + j) * 1024);
+        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(gsrc[j] + kt * gstep[j]), "s"(la)
+                     : "memory", "m0");
+    };
     auto issue_loads = [&](int64_t kt, int buf) {
-        uint8_t *dst = smem + buf * STAGE + wave_u * NLD * 1024;
 #pragma unroll
-        for (int j = 0; j < NLD; ++j) {
-            const uint32_t la = (uint32_t)(uintptr_t)(dst + j * 1024);
-            asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                         :
-                         : "v"(gsrc[j] + kt * gstep[j]), "s"(la)
-                         : "memory", "m0");
-        }
+        for (int j = 0; j < NLD; ++j) issue_one(kt, buf, j);
     };
     static_assert(PAIR8 || RPL * NCH == 64, "lane layout");
 
@@ -387,7 +387,23 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 for (int m = 0; m < MI; ++m)
                     f[NLP + p][m] = *(const u32x4 *)(base + (NLP + p) * PANEL + roff_b[m] + ((cl ^ key_b[m]) << 4));
         };
-        auto mfmas = [&](const Frag &f) {
+        // Loads of the next K-tile still to issue in this iteration: they go
+        // out one after each MFMA block of the first substeps (il), since as
+        // one burst after the barrier they left the MFMA pipe idle while they
+        // issued (10% of the plain product's time at n = 10^4).
+        int64_t ktl = 0;
+        int bufl = 0, jl = 0;
+        auto il = [&](int jend) {
+            if (jl < jend) {
+                issue_one(ktl, bufl, jl);
+                ++jl;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        };
+        constexpr int ILS = NSUB >= 2 ? 2 : 1;           // substeps that carry loads
+        constexpr int LPS = (NLD + ILS - 1) / ILS;       // loads per such substep
+        auto jend_of = [](int sub) { return sub < ILS ? ((sub + 1) * LPS < NLD ? (sub + 1) * LPS : NLD) : NLD; };
+        auto mfmas = [&](const Frag &f, int jend) {
 #pragma unroll
             for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -404,6 +420,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                     } else {
                         mma(acc[mi][ni], f[0][mi], f[NLP][ni], T{});
                     }
+                    il(jend);
                 }
         };
         // ds_read_b128 per K-unit; the counter holds 15 at most, and a wait for
@@ -431,8 +448,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 // stage (kr - 1) mod NST was last read in iteration kt - 1, which every
                 // wave finished before the barrier that ended it
                 const int64_t tn = kt + NST - 1;
-                issue_loads(tn < ke ? tn : ke - 1, (int)((kr + NST - 1) % NST));
-                __builtin_amdgcn_sched_barrier(0);
+                ktl = tn < ke ? tn : ke - 1;
+                bufl = (int)((kr + NST - 1) % NST);
+                jl = 0;
 #pragma unroll
                 for (int sub = 0; sub < NSUB; ++sub) {
                     // next substep's fragments first, then this substep's MFMAs on
@@ -442,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         load_frags(base, sub + 1, fr[(sub + 1) & 1]);
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<NDS>();
-                        mfmas(fr[sub & 1]);
+                        mfmas(fr[sub & 1], jend_of(sub));
                     } else if constexpr (PAIR8) {
                         // the unit's reads were issued in groups (substep 0, substep
                         // 1, codes): start on each group as it lands; every
@@ -453,13 +471,19 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma unroll
                         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-                            for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                            for (int ni = 0; ni < MI; ++ni) {
+                                mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
+                                il(MI * MI < NLD ? MI * MI : NLD);
+                            }
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<2 * MI>();
 #pragma unroll
                         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-                            for (int ni = 0; ni < MI; ++ni) mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                            for (int ni = 0; ni < MI; ++ni) {
+                                mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
+                                il(NLD);
+                            }
                         u32x4 ha[MI], hb[MI];
 #pragma unroll
                         for (int m = 0; m < MI; ++m) {
@@ -475,10 +499,14 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                     } else {
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<0>();
-                        mfmas(fr[sub & 1]);
+                        mfmas(fr[sub & 1], jend_of(sub));
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                // any loads the MFMA blocks had no room for
+#pragma unroll
+                for (int j = 0; j < NLD; ++j)
+                    if (j >= jl) issue_one(ktl, bufl, j);
                 // Tile kt + 1 landed for this wave, then (barrier) for all waves. A
                 // plain s_barrier: a fenced __syncthreads would wait for every
                 // outstanding load (vmcnt(0)) and undo the prefetch. Every ds_read of
