@@ -541,6 +541,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const IoArg io = io_of(g.io_tab, g.io0, tv.x);
         const float hl = 0.5f * (float)dm.scal->lam * acc_scale;
         const int64_t n = dm.n;
+        // four consecutive rows of one column as one 16-byte access where aligned
+        const bool vec = ((reinterpret_cast<uintptr_t>(io.X) | reinterpret_cast<uintptr_t>(io.out)) & 15) == 0 &&
+                         (io.ld & 3) == 0;
 #pragma clang loop unroll(full)
         for (int mi = 0; mi < MIE; ++mi)
 #pragma clang loop unroll(full)
@@ -550,6 +553,18 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                     const int64_t ib = i0 + wr + (mi + mo) * 32 + 8 * eg + 4 * (lane >> 5);
                     const int64_t j = j0 + wc + (ni + no) * 32 + (lane & 31);
                     if (j >= n || ib >= n) continue;
+                    if (vec && !diag && ib + 3 < n) {
+                        // strictly upper rows ib..ib+3 of column j: read, then written by
+                        // this thread only (out == X is safe)
+                        const f32x4 x = *(const f32x4 *)(io.X + j * io.ld + ib);
+                        f32x4 v;
+#pragma clang loop unroll(full)
+                        for (int q = 0; q < 4; ++q) v[q] = 0.5f * x[q] + hl * acc[mi][ni][4 * eg + q];
+                        *(f32x4 *)(io.out + j * io.ld + ib) = v;
+#pragma clang loop unroll(full)
+                        for (int q = 0; q < 4; ++q) io.out[(ib + q) * io.ld + j] = v[q];
+                        continue;
+                    }
 #pragma clang loop unroll(full)
                     for (int q = 0; q < 4; ++q) {
                         const int64_t i = ib + q;
