@@ -251,7 +251,7 @@ def _with_tuning(settings, fn):
         P.tune("gemm_tile", 0)
 
 
-@pytest.mark.parametrize("mode", ["fp16", "fp8_fp16_split"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp32_emu"])
 def test_ksplit_tail_tiles(mode):
     """Tail tiles cut into K-chunks (forced: 256 tiles from n = 512 and a tail
     rule for 64 CUs, so all 21 tiles of n = 1500 form the tail, 3 chunks
@@ -275,7 +275,7 @@ def test_ksplit_tail_tiles(mode):
     ref, _ = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"])
     out = a.cpu().numpy()
     assert rel_fro(out, ref) <= TOL_POLY[mode]
-    assert rel_fro(out, ref_t.cpu().numpy()) <= TOL_POLY[mode]
+    assert rel_fro(out, ref_t.cpu().numpy()) <= 2 * TOL_POLY[mode]  # both within TOL of the oracle
 
 
 def test_ksplit_more_chunks_than_k_tiles():
