@@ -77,3 +77,32 @@ def pair8_pack(lo_codes):
 def pair8_unpack(buf):
     n = buf.shape[0]
     return np.ascontiguousarray(buf.ravel()[pair8_index(n)])
+
+
+def rocsolver_eigh64(X):
+    """FP64 eigendecomposition of a symmetric device matrix with rocSOLVER's
+    dsyevd (the library reference of the full-size tests; its upper triangle,
+    read as column-major, is the matrix). Returns (w, Q) on the device with
+    the eigenvectors in the rows of Q, so that X = Q^T diag(w) Q."""
+    import ctypes
+    import torch
+    blas = ctypes.CDLL("librocblas.so")
+    sol = ctypes.CDLL("librocsolver.so")
+    h = ctypes.c_void_p()
+    assert blas.rocblas_create_handle(ctypes.byref(h)) == 0
+    try:
+        st = torch.cuda.current_stream()
+        assert blas.rocblas_set_stream(h, ctypes.c_void_p(st.cuda_stream)) == 0
+        n = X.shape[0]
+        A = X.double().contiguous().clone()
+        w = torch.empty(n, dtype=torch.float64, device=X.device)
+        E = torch.empty(n, dtype=torch.float64, device=X.device)
+        info = torch.zeros(1, dtype=torch.int32, device=X.device)
+        # rocblas_evect_original = 211, rocblas_fill_upper = 121
+        assert sol.rocsolver_dsyevd(h, 211, 121, n, ctypes.c_void_p(A.data_ptr()), n, ctypes.c_void_p(w.data_ptr()),
+                                    ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(info.data_ptr())) == 0
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        return w, A
+    finally:
+        blas.rocblas_destroy_handle(h)
