@@ -119,7 +119,16 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
 
 /* Batched projection of `count` independent matrices (host arrays of sizes,
  * leading dimensions and device pointers). Matrices are independent; each
- * result equals the one psdproj_project gives for that matrix alone. */
+ * result equals the one psdproj_project gives for that matrix alone.
+ *
+ * Graph capture (this call and psdproj_project / _ex): a call that repeats
+ * the previous call on the same stream (same sizes, mode, options and
+ * pointers) issues kernel launches only and may be captured into a HIP
+ * graph; make the call once uncaptured first. A batched call whose pointers
+ * differ from the previous one returns PSDPROJ_ERR_UNSUPPORTED while the
+ * stream is capturing. A captured graph uses the stream's workspace: a later
+ * call on that stream with other sizes or mode, psdproj_release or
+ * psdproj_tune invalidates it. */
 int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld,
                             const float *const *X, float *const *out, int mode,
                             psdproj_stream_t stream);

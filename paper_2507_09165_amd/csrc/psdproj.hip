@@ -181,9 +181,12 @@ struct Plan {
     std::vector<MatLayout> mats;
     // arena the device tables were built for
     void *base = nullptr;
-    // pinned staging of the per-call I/O table (multi-matrix plans)
+    // pinned staging of the per-call I/O table (multi-matrix plans), and the
+    // table last uploaded to the arena (io_valid: it is still there)
     IoArg *io_host = nullptr;
     hipEvent_t io_done = nullptr;
+    std::vector<IoArg> io_last;
+    bool io_valid = false;
 
     ~Plan() {
         if (io_done) (void)hipEventDestroy(io_done);
@@ -238,6 +241,7 @@ void layout_plan(Plan &P) {
 // tables being replaced.
 int build_tables(Plan &P, void *base, hipStream_t s) {
     const size_t M = P.ns.size();
+    P.io_valid = false;
     uint8_t *b = (uint8_t *)base;
     std::vector<MatDesc> desc(M);
     std::vector<WorkItem> wv, wt, wc;
@@ -369,7 +373,16 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
     if (M == 1) {
         B.io_tab = nullptr;
         B.io0 = ios[0];
+    } else if (P.io_valid && !memcmp(P.io_last.data(), ios, sizeof(IoArg) * M)) {
+        // the same buffers as the last call: the table in the arena is current,
+        // so the call is kernel launches only (and can be captured in a graph)
+        B.io_tab = (const IoArg *)(b + P.off_io);
     } else {
+        // A new table is uploaded through pinned staging with a host-side wait,
+        // which stream capture cannot record: capture only repeated calls.
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return PSDPROJ_ERR_UNSUPPORTED;
         // per-call I/O table: pinned staging, reused once its last upload ran
         if (!P.io_host) {
             if (hipHostMalloc((void **)&P.io_host, sizeof(IoArg) * M, hipHostMallocDefault) != hipSuccess)
@@ -380,9 +393,12 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
         }
         memcpy(P.io_host, ios, sizeof(IoArg) * M);
         IoArg *io_dev = (IoArg *)(b + P.off_io);
+        P.io_valid = false;
         if (hipMemcpyAsync(io_dev, P.io_host, sizeof(IoArg) * M, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipEventRecord(P.io_done, s) != hipSuccess)
             return PSDPROJ_ERR_HIP;
+        P.io_last.assign(ios, ios + M);
+        P.io_valid = true;
         B.io_tab = io_dev;
     }
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
@@ -479,7 +495,15 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
     StagePlan sp;
     if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
     Pool &pool = g_pool[{dev, s}];
+    // Rebuilding a plan, growing the workspace or uploading tables wait on
+    // the host, which stream capture cannot record: refuse them while the
+    // stream is capturing (queried only when one of them is due).
+    auto capturing = [&]() {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    };
     if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns)) {
+        if (capturing()) return PSDPROJ_ERR_UNSUPPORTED;
         std::unique_ptr<Plan> P(new Plan());
         P->mode = o.mode;
         P->steps = steps;
@@ -498,6 +522,7 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
         pool.plan = std::move(P);
     }
     Plan &P = *pool.plan;
+    if ((pool.bytes < P.total || P.base != pool.ptr) && capturing()) return PSDPROJ_ERR_UNSUPPORTED;
     void *base = nullptr;
     const int st = get_workspace(pool, s, P.total, &base);
     if (st != PSDPROJ_OK) return st;
