@@ -139,9 +139,10 @@ __device__ __forceinline__ void wait_lgkmcnt() {
     __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (N << 8) | (3 << 14));
 }
 
-// X8: split parts are FP8 pairs (FP16 hi + e4m3 hi/lo codes) instead of FP16
-// hi + FP16 lo; the pair product is L_hi R_hi on FP16 MFMAs plus both cross
-// terms on one FP8 MFMA per 32 K. Requires T = f16 and LS == RS.
+// X8: split parts are FP8 pairs (FP16 hi + stored e4m3 lo codes; the hi
+// codes are formed in registers) instead of FP16 hi + FP16 lo; the pair
+// product is L_hi R_hi on FP16 MFMAs plus both cross terms on one FP8 MFMA per
+// 32 K. Requires T = f16 and LS == RS.
 //
 // COMB (both operands split, 128 tile): each operand's LDS row interleaves
 // its two parts, [hi of BK K | lo (or FP8 pair) of the same BK K], so two
@@ -154,8 +155,9 @@ __device__ __forceinline__ void wait_lgkmcnt() {
 // buffer, no epilogue); 2 = fixup of a split tile (entry {matrix, tile,
 // chunks << 8, first partial}; sums the chunks' partials in chunk order, then
 // the epilogue). A fixup workgroup covers one 32 x 32 MFMA block (mi, ni) of
-// every wave, so a tile's fixup is spread over MI^2 workgroups. The split tiles are the few that would otherwise leave most CUs
-// idle in a last, partial round of 256 tiles.
+// every wave, so a tile's fixup is spread over MI^2 workgroups. The split
+// tiles are the few that would otherwise leave most CUs idle in a last,
+// partial round of 256 tiles.
 template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8, int KS>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     static_assert(!X8 || (sizeof(T) == 2 && LS == RS), "FP8 pairs: FP16 hi, both operands split");
@@ -684,19 +686,20 @@ void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T) {
                     if (bi <= bj) v.push_back(WorkItem{m, (uint32_t)bi | ((uint32_t)bj << 16)});
 }
 
-// The 128 tile (two workgroups per CU) measured faster than the 256 tile at
-// n = 10^4 (37.1 vs 38.0 ms for a plain FP16 projection), so it is the default;
-// the 256 tile remains available through the tuning hook.
+// Tile edge of the kernel-level entry points (one launch over the whole
+// triangle): 128, or the tile override where it divides K. The projection's
+// own products pick tiles per matrix (gemm_use_big, gemm_tile_lists).
 int gemm_pick_tile(int64_t K, int dtype) {
     const int o = g_tile_override;
     if (o && K % o == 0) return o;
     return 128;
 }
 
-// Plain products of large FP16/BF16 matrices run on the 256 tile: it moves
-// half the operand bytes per flop of the 128 tile, and the products are bound
-// by moving operands into LDS. Matrices smaller than this stay on 128 tiles.
-// (Tuning hooks: the size threshold, and the CU count the tail rule uses.)
+// Products of large FP16/BF16 matrices run on the 256 tile: it moves half the
+// operand bytes per flop of the 128 tile (one workgroup per CU against two).
+// Matrices smaller than this stay on 128 tiles, where a round of 256 tiles
+// would leave most CUs idle. (Tuning hooks: the size threshold, and the CU
+// count the tail rule uses.)
 static int64_t g_big_min = 6144;
 static int g_tail_cus = 0;  // 0: the device's CU count
 
@@ -722,9 +725,10 @@ void gemm_set_split_big(int mask) {
 }
 
 // Padded order of the work matrices: a multiple of 256 where the 256 tile is
-// used, else of 128 (or of the override). Any choice gives bitwise-identical
-// results: every element accumulates its K products in the same order
-// whatever the tile shape, and padding only adds zeros.
+// used, else of 128 (or of the override). Whole tiles of either size give
+// bitwise-identical results: every element accumulates its K products in the
+// same order whatever the tile shape, and padding only adds zeros (K-split
+// tail tiles differ from that by rounding).
 int64_t gemm_padded_size(int64_t n, bool big) {
     const int64_t m = n > 0 ? n : 1;
     if (big) return round_up(m, 256);
@@ -796,10 +800,12 @@ void gemm_set_ksplit_max(int c) {
 // 64-byte rows (measured 1.7% faster per split projection than one 128-KB
 // workgroup per CU). Deeper rings measured slower at n = 10^4 for the plain
 // product (1.20 ms per product with this ring; 1.36-1.52 ms with 3-5 stages of
-// 64- or 128-byte rows at one or two workgroups per CU). The 256 tile uses
-// 128 KB: two stages of 128-byte rows for plain operands (faster than a
-// 4-stage ring of 64-byte rows: 1.27 vs 1.31 ms at n_p = 10240), two of
-// 64-byte rows for split ones.
+// 64- or 128-byte rows at one or two workgroups per CU), and 64-byte rows at
+// four workgroups per CU slowed the batch of small matrices by 8%. The 256
+// tile uses 128 KB: two stages of 128-byte rows for plain operands (faster
+// than 3- or 4-stage rings of 64-byte rows by 4-8% at n_p = 10240), two of
+// 64-byte rows for split ones; FP8 pairs use 96 KB (a 3-stage ring of them
+// with an earlier barrier measured 4% slower).
 template <int BM, int NP> struct LdsCfg {
     static constexpr bool COMB = BM == 128 && NP == 4;  // two parts per 128-byte row
     static constexpr int NST = 2;
