@@ -84,3 +84,22 @@ def test_status_strings():
     L = P.lib()
     assert L.psdproj_status_string(0) == b"ok"
     assert L.psdproj_status_string(3) == b"out of device memory"
+
+
+def test_tuning_keys_validate_their_values():
+    """psdproj_tune: unknown keys and out-of-range values are rejected; the
+    host-only keys accept their documented values (defaults restored)."""
+    L = P.lib()
+    t = lambda k, v: L.psdproj_tune(k.encode(), ctypes.c_int64(v))
+    assert t("no_such_key", 1) != 0
+    for key, bad in (("gemm_tile", 64), ("gemm_big_min", 0), ("gemm_tail_cus", -1), ("gemm_split_big", 4),
+                     ("gemm_ksplit", 0), ("gemm_block", 0), ("work_ld_pad", 100), ("work_ld_pad", -64)):
+        assert t(key, bad) == 1, (key, bad)
+    try:
+        for key, ok in (("gemm_tile", 256), ("gemm_tile", 128), ("gemm_big_min", 512), ("gemm_tail_cus", 64),
+                        ("gemm_split_big", 0), ("gemm_ksplit", 1), ("gemm_block", (4 << 8) | 4)):
+            assert t(key, ok) == 0, (key, ok)
+    finally:
+        for key, v in (("gemm_tile", 0), ("gemm_big_min", 6144), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
+                       ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4)):
+            assert t(key, v) == 0
