@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--no-rocsolver", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg (256 blocks) and print its JSON")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -311,6 +313,9 @@ def main():
         return
 
     P.lib()
+    if args.batched_only:
+        print(json.dumps(batched_leg()), flush=True)
+        return
     dev = torch.device("cuda:0")
     n = args.n
     log("generating input", args.input, n)
