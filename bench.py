@@ -121,7 +121,7 @@ def gemm_roofline(X, out, opts, n, mode, stream):
     for v in classes.values():
         v["tflops_per_product_equivalent"] = flops / (v["avg_ms"] * 1e-3) / 1e12
     tr = measured_traffic(mode) if n == 10000 else None
-    res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection products; from n = 6144 one "
+    res = {"kernel": f"gemm_sym_kernel<{dt}, plain stage product> (in-projection products; from n = 5633 one "
                      "product is a launch of 256 x 256 tiles over whole rounds, a launch of the last round's "
                      "tiles cut into K-chunks, and their fixup)",
            "bound": "mfma",

@@ -153,7 +153,7 @@ int psdproj_release(void);
 const char *psdproj_status_string(int status);
 
 /* Tuning hook (process-wide, not thread-safe against concurrent launches).
- * By default the products of matrices with n >= 6144 (FP16/BF16 modes) run
+ * By default the products of matrices with n >= 5633 (FP16/BF16 modes) run
  * their whole rounds of 256 x 256 tiles (one workgroup per CU). The tiles of
  * a last partial round are cut into K-chunks that run side by side (FP32
  * partials summed in chunk order by a fixup) when they fill at most half the

@@ -697,10 +697,12 @@ int gemm_pick_tile(int64_t K, int dtype) {
 
 // Products of large FP16/BF16 matrices run on the 256 tile: it moves half the
 // operand bytes per flop of the 128 tile (one workgroup per CU against two).
-// Matrices smaller than this stay on 128 tiles, where a round of 256 tiles
-// would leave most CUs idle. (Tuning hooks: the size threshold, and the CU
-// count the tail rule uses.)
-static int64_t g_big_min = 6144;
+// From n = 5633 (n_p = 5888, 276 tiles) a matrix fills at least one whole
+// round of 256 CUs; below, all its 256-tiles would be tail (as 128 tiles, at
+// a coarser padding). Measured at n = 5782: 8.8 against 10.1 ms (FP8 pairs);
+// equal at 4096-5000, 2-9% slower at 2048-3072. (Tuning hooks: the size
+// threshold, and the CU count the tail rule uses.)
+static int64_t g_big_min = 5633;
 static int g_tail_cus = 0;  // 0: the device's CU count
 
 bool gemm_use_big(int64_t n, int dtype) {

@@ -724,7 +724,7 @@ int psdproj_release(void) {
     return PSDPROJ_OK;
 }
 
-static int64_t g_big_min_hook = 6144;
+static int64_t g_big_min_hook = 5633;
 static int g_tail_cus_hook = 0;
 
 int psdproj_gemm_timing_start(void) {

@@ -231,7 +231,7 @@ def test_mixed_tile_sizes_bitwise_equal(mode):
         torch.cuda.synchronize()
     finally:
         P.tune("gemm_tail_cus", 0)
-        P.tune("gemm_big_min", 6144)
+        P.tune("gemm_big_min", 5633)
         P.tune("gemm_tile", 0)
     assert torch.equal(ref_t, mix_t)
     info = P.read_info(info_t)
@@ -247,7 +247,7 @@ def _with_tuning(settings, fn):
     finally:
         P.tune("gemm_ksplit", 8)
         P.tune("gemm_tail_cus", 0)
-        P.tune("gemm_big_min", 6144)
+        P.tune("gemm_big_min", 5633)
         P.tune("gemm_tile", 0)
 
 

@@ -100,6 +100,6 @@ def test_tuning_keys_validate_their_values():
                         ("gemm_split_big", 0), ("gemm_ksplit", 1), ("gemm_block", (4 << 8) | 4)):
             assert t(key, ok) == 0, (key, ok)
     finally:
-        for key, v in (("gemm_tile", 0), ("gemm_big_min", 6144), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
+        for key, v in (("gemm_tile", 0), ("gemm_big_min", 5633), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
                        ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4)):
             assert t(key, v) == 0
