@@ -151,18 +151,27 @@ def lanczos_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZO
     return {"lam": lam, "sigma": sigma, "r": r, "k": k}
 
 
-def spectral_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS):
+def spectral_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, force_fallback: bool = False):
     """Lanczos bound with the guard and the Frobenius cap. Returns dict with
-    lam, fro, colmax, fallback (bool) and the Lanczos fields."""
+    lam (the bound used), lanczos_lam (sqrt(sigma + r) before the guard),
+    fro, colmax, fallback (bool) and the Lanczos fields.
+
+    Guard: a bound below the largest column norm (itself a lower bound on
+    ||X||_2) is invalid and is replaced by ||X||_F. Cap: the bound never
+    exceeds ||X||_F, which is also an upper bound on ||X||_2.
+    ``force_fallback`` halves the Lanczos bound before the guard, so that the
+    guard's branch can be exercised on any input (the library has the same
+    test hook)."""
     fro = float(np.sqrt(np.sum(Xs * Xs)))
     colmax = float(np.sqrt(np.max(np.sum(Xs * Xs, axis=0)))) if Xs.size else 0.0
     out = {"fro": fro, "colmax": colmax}
     if fro == 0.0:
-        out.update(lam=0.0, sigma=0.0, r=0.0, k=0, fallback=False)
+        out.update(lam=0.0, lanczos_lam=0.0, sigma=0.0, r=0.0, k=0, fallback=False)
         return out
     lz = lanczos_bound(Xs, steps)
     out.update(lz)
-    lam = lz["lam"]
+    out["lanczos_lam"] = lz["lam"]
+    lam = 0.5 * lz["lam"] if force_fallback else lz["lam"]
     fallback = not (lam >= colmax)
     if fallback:
         lam = fro
@@ -193,8 +202,22 @@ def g_scalar(x, mode: str = "fp16"):
     return 0.5 * x * (1.0 + composite_scalar(x, stage_rows(mode)))
 
 
+def filter_stage(Y: np.ndarray, a: float, b: float, c: float) -> np.ndarray:
+    """One odd quintic stage f(Y) = a Y + b Y^3 + c Y^5 of Algorithm 2, with
+    the three matrix products A = Y Y, B = b A + c A A, Y' = a Y + Y B."""
+    A = Y @ Y
+    B = b * A + c * (A @ A)
+    return a * Y + Y @ B
+
+
+def final_combine(X0: np.ndarray, Y: np.ndarray, lam: float) -> np.ndarray:
+    """Return step of Algorithm 2: lam X0 (I + X_T) / 2, symmetrised."""
+    P = lam * 0.5 * (X0 + X0 @ Y)
+    return 0.5 * (P + P.T)
+
+
 def project_poly(X, mode: str = "fp16", lam: float | None = None,
-                 steps: int = LANCZOS_STEPS):
+                 steps: int = LANCZOS_STEPS, force_fallback: bool = False):
     """Algorithm 2 in FP64. ``lam`` overrides the spectral bound (so that the
     oracle evaluates exactly the function the device evaluated).
 
@@ -206,7 +229,7 @@ def project_poly(X, mode: str = "fp16", lam: float | None = None,
     if not np.all(np.isfinite(Xs)):
         raise ValueError("non-finite input")
     if lam is None:
-        info = spectral_bound(Xs, steps)
+        info = spectral_bound(Xs, steps, force_fallback)
         lam = info["lam"]
     else:
         info = {"lam": float(lam), "fro": float(np.sqrt(np.sum(Xs * Xs)))}
@@ -215,12 +238,8 @@ def project_poly(X, mode: str = "fp16", lam: float | None = None,
     X0 = Xs / lam
     Y = X0
     for a, b, c in stage_rows(mode):
-        A = Y @ Y
-        B = b * A + c * (A @ A)
-        Y = a * Y + Y @ B
-    P = lam * 0.5 * (X0 + X0 @ Y)
-    P = 0.5 * (P + P.T)
-    return P, info
+        Y = filter_stage(Y, a, b, c)
+    return final_combine(X0, Y, lam), info
 
 
 def gemm_count(mode: str) -> int:

@@ -195,6 +195,60 @@ def test_bound_zero_matrix():
     assert b["lam"] == 0.0
 
 
+def _golden_start_pair():
+    """Normalised Lanczos start vector of order 2, from the SplitMix64 known
+    answers (entries 2 (z >> 11) 2^-53 - 1), computed here without the
+    oracle's generator."""
+    z = []
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                z.append(int(line, 16))
+    v = np.array([2.0 * (zi >> 11) * 2.0 ** -53 - 1.0 for zi in z[:2]])
+    return v / np.linalg.norm(v)
+
+
+def test_bound_one_step_closed_form_cap_and_guard():
+    """Theorem 2 with a single Lanczos step on X = s * diag(1, 0) or
+    s * diag(0, 1): q is the start vector (c, d), sigma = s^2 c^2 (resp.
+    s^2 d^2) and ||X^2 q - sigma q|| = s^2 |c d|, so the raw bound is
+    s sqrt(c^2 + |c d|) (resp. s sqrt(d^2 + |c d|)). With |c| > |d| the first
+    exceeds ||X||_F = s and must be capped to it; the second falls below the
+    column-norm lower bound s and the guard must replace it by ||X||_F."""
+    c, d = _golden_start_pair()
+    assert abs(c) > abs(d)
+    s = 3.0
+    cap = oracle.spectral_bound(np.diag([s, 0.0]), steps=1)
+    raw_cap = s * np.sqrt(c * c + abs(c * d))
+    assert raw_cap > s
+    assert cap["lanczos_lam"] == pytest.approx(raw_cap, rel=1e-13)
+    assert cap["lam"] == pytest.approx(s, rel=1e-15) and not cap["fallback"]
+    guard = oracle.spectral_bound(np.diag([0.0, s]), steps=1)
+    raw_guard = s * np.sqrt(d * d + abs(c * d))
+    assert raw_guard < s
+    assert guard["lanczos_lam"] == pytest.approx(raw_guard, rel=1e-13)
+    assert guard["lam"] == pytest.approx(s, rel=1e-15) and guard["fallback"]
+    assert guard["colmax"] == pytest.approx(s, rel=1e-15)
+
+
+def test_bound_forced_fallback_gives_frobenius():
+    """The guard's branch on a larger input: with the Lanczos bound halved
+    (test hook) it falls below max_j ||X e_j|| = max |d_i| of a diagonal
+    matrix, so the bound becomes ||X||_F = ||d||_2 and the fallback is
+    reported; without the hook the same matrix keeps its Lanczos bound."""
+    d = np.array([0.5, -3.0, 2.0, 1e-3, -2.9, 1.25])
+    plain = oracle.spectral_bound(np.diag(d))
+    assert not plain["fallback"] and plain["lam"] < np.linalg.norm(d)
+    forced = oracle.spectral_bound(np.diag(d), force_fallback=True)
+    assert forced["fallback"]
+    assert forced["lam"] == pytest.approx(np.linalg.norm(d), rel=1e-15)
+    assert forced["lanczos_lam"] == pytest.approx(plain["lanczos_lam"], rel=1e-15)
+    P, info = oracle.project_poly(np.diag(d), "fp16", force_fallback=True)
+    assert info["fallback"] and info["lam"] == forced["lam"]
+    lam = forced["lam"]
+    np.testing.assert_allclose(np.diag(P), lam * oracle.g_scalar(d / lam, "fp16"), rtol=1e-12, atol=1e-15)
+
+
 # --------------------------------------------------------------------------
 # Composite polynomial projection (Algorithm 2)
 # --------------------------------------------------------------------------
