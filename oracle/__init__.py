@@ -6,6 +6,7 @@ HIP library (``paper_2507_09165_amd``), and the library never imports it.
 """
 from .psd import (  # noqa: F401
     efloat,
+    efloat_rows,
     filter_stage,
     final_combine,
     g_scalar,

@@ -295,6 +295,12 @@ def efloat(table: str, with_rescale: bool = False):
     """Returns (twice_err, argmax): max over float32 x in [0, 1] of
     |x p(x) - x|. The literal ReLU error of eq. (12) is half of it."""
     rows = tables.runtime_table(table) if with_rescale else tables.TABLES[table]
+    return efloat_rows(rows)
+
+
+def efloat_rows(rows):
+    """``efloat`` for any T x 3 table of odd quintic stages (a, b, c)."""
+    rows = np.asarray(rows, dtype=np.float64)
     abc = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1)
     arg = ctypes.c_double(0.0)
     e = _lib().oracle_efloat(rows.shape[0], _dp(abc), ctypes.byref(arg))
