@@ -23,8 +23,9 @@
  *     default stream) and returns. The return value reports argument, launch
  *     and allocation errors only; numerical status (non-finite input, bound
  *     fallback, lam) is written to device memory (psdproj_info).
- *   - n == 0 is a no-op. X == 0 gives out == 0. A non-finite input leaves out
- *     unmodified and sets psdproj_info.nonfinite.
+ *   - n == 0 is a no-op. X == 0 gives out == 0. A non-finite input (Inf or NaN
+ *     in the upper triangle) sets every entry of out to NaN and sets
+ *     psdproj_info.nonfinite, so callers without an info buffer see it too.
  *   - The library keeps a workspace per (device, stream), grown on demand
  *     (growing synchronises that stream). Calls on one stream are ordered by
  *     the stream; calls on different streams use different workspaces.
@@ -52,14 +53,18 @@ typedef enum {
     PSDPROJ_ERR_CANCELLED = 6,
     PSDPROJ_ERR_TIMEOUT = 7,
     PSDPROJ_ERR_NOT_FOUND = 8,
-    PSDPROJ_ERR_PENDING = 9
+    PSDPROJ_ERR_PENDING = 9,
+    PSDPROJ_ERR_NONFINITE = 10 /* served request whose input held Inf/NaN */
 } psdproj_status;
 
 /* Compute precision of the filter products. Storage of X and out is FP32. */
 typedef enum {
     PSDPROJ_MODE_FP32 = 0,       /* Table 1 refined (T = 10), FP32 MFMA, 31 products  */
     PSDPROJ_MODE_FP16 = 1,       /* Table 2 refined (T = 7), FP16 MFMA, 22 products   */
-    PSDPROJ_MODE_BF16 = 2,       /* Table 2 refined (T = 7), BF16 MFMA, 22 products   */
+    PSDPROJ_MODE_BF16 = 2,       /* Table 2 refined (T = 7), BF16 MFMA; by default the
+                                    products of stages 1-4 use BF16 hi+lo split
+                                    operands (plain BF16, 8 significant bits, misses
+                                    the 5e-3 half-precision target): 46 products   */
     PSDPROJ_MODE_FP16_SPLIT = 3, /* Table 2 refined, FP16 with hi+lo split operands in
                                     the stages of split_mask and the final product   */
     PSDPROJ_MODE_FP32_EMU = 4,   /* Table 1 refined (T = 10), every product on FP16
@@ -77,10 +82,13 @@ typedef enum {
 typedef struct {
     int mode;                 /* psdproj_mode */
     int lanczos_steps;        /* 0 -> 20 (Section 3.4); at most 32 */
-    uint32_t split_mask;      /* FP16_SPLIT, FP8_FP16_SPLIT: bit t set -> stage t+1
-                                 uses split products; 0 -> library default */
-    int split_final;          /* FP16_SPLIT, FP8_FP16_SPLIT: -1 default, 0 plain,
-                                 1 split final product */
+    uint32_t split_mask;      /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: bit t set ->
+                                 stage t+1 uses split products; 0 -> the mode's
+                                 default (stages 2-3; BF16: 1-4). Bit 31 set:
+                                 bits 0..30 are taken as given even when all zero
+                                 (e.g. 0x80000000 = no split stage) */
+    int split_final;          /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: -1 default (0),
+                                 0 plain, 1 split final product */
     double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */
     int force_bound_fallback; /* test hook: halve the Lanczos bound so that the
                                  guard must replace it by ||X||_F */
@@ -95,7 +103,7 @@ typedef struct {
     double fro_norm;       /* ||X||_F */
     double colmax_norm;    /* max_j ||X e_j||_2 (lower bound on ||X||_2) */
     int32_t lanczos_steps; /* Lanczos steps taken (early stop on breakdown) */
-    int32_t nonfinite;     /* input held Inf/NaN; out was not written */
+    int32_t nonfinite;     /* input held Inf/NaN; out was set to NaN */
     int32_t fallback;      /* guard replaced an invalid Lanczos bound */
     int32_t stages;        /* filter stages applied */
 } psdproj_info;
@@ -121,17 +129,30 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
  * leading dimensions and device pointers). Matrices are independent; each
  * result equals the one psdproj_project gives for that matrix alone.
  *
- * Graph capture (this call and psdproj_project / _ex): a call that repeats
- * the previous call on the same stream (same sizes, mode, options and
- * pointers) issues kernel launches only and may be captured into a HIP
- * graph; make the call once uncaptured first. A batched call whose pointers
- * differ from the previous one returns PSDPROJ_ERR_UNSUPPORTED while the
- * stream is capturing. A captured graph uses the stream's workspace: a later
- * call on that stream with other sizes or mode, psdproj_release or
+ * Graph capture (this call and psdproj_project / _ex / _batched_ex): a call
+ * with the sizes, mode and options of the previous call on the same stream
+ * issues kernel launches only and may be captured into a HIP graph; make the
+ * call once uncaptured first. A batched call keeps its table of caller
+ * pointers in a ring of 8 tables per (stream, sizes, mode): a call whose
+ * pointers are in the ring uploads nothing, and a table that a captured call
+ * used is never overwritten afterwards, so later calls with other pointers
+ * (e.g. ping-pong iterate buffers) leave earlier graphs valid. While the
+ * stream is capturing, a batched call whose pointers are not in the ring, or
+ * any call that needs a new plan or more workspace, returns
+ * PSDPROJ_ERR_UNSUPPORTED; so does an uncaptured call when all 8 tables are
+ * held by captures. A captured graph uses the stream's workspace: a later call
+ * on that stream with other sizes, mode or options, psdproj_release or
  * psdproj_tune invalidates it. */
 int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld,
                             const float *const *X, float *const *out, int mode,
                             psdproj_stream_t stream);
+
+/* As psdproj_project_batched with options; info_dev (device memory, count
+ * entries, may be NULL) receives each matrix's numerical status at index i
+ * (entries of matrices with n[i] == 0 are not written). */
+int psdproj_project_batched_ex(const psdproj_opts *opts, int count, const int64_t *n,
+                               const int64_t *ld, const float *const *X, float *const *out,
+                               psdproj_stream_t stream, psdproj_info *info_dev);
 
 /* Device bytes of workspace a projection of size n in `mode` uses. */
 size_t psdproj_workspace_bytes(int64_t n, int mode);
@@ -210,7 +231,8 @@ typedef struct {
 } psdproj_request;
 
 typedef struct {
-    int status;      /* PSDPROJ_OK, _REJECTED, _CANCELLED, _HIP, ... */
+    int status;      /* PSDPROJ_OK, _NONFINITE (input held Inf/NaN; out is NaN),
+                        _REJECTED, _CANCELLED, _HIP, ... */
     int mode;
     uint64_t tag;
     int64_t submit_ns, start_ns, end_ns;

@@ -59,6 +59,7 @@ struct IoArg {
     const float *X;
     float *out;
     int64_t ld;
+    void *info;  // psdproj_info in device memory, or null
 };
 
 // (matrix, local block) pair of a work list.

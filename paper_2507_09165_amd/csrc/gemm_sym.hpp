@@ -42,6 +42,10 @@ struct GemmArgs {
 // g.split and for bm = 256 only.
 hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool rs, int bm, int64_t ntiles,
                            hipStream_t s, int ks = 0);
+// One (precision, epilogue) slice of gemm_sym_launch, explicitly instantiated
+// in gemm_launch_*.hip.
+template <int DT, int EPI>
+hipError_t gemm_launch_part(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s, int ks);
 // Append matrix m's upper tiles (T x T tile grid) in the blocked schedule order.
 void append_tile_order(std::vector<WorkItem> &v, uint32_t m, int T);
 
@@ -70,9 +74,14 @@ void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &bi
 int gemm_tile_generation();
 // CU count the tail rule uses (the device's unless the tuning hook set one).
 int gemm_tail_cus(int device_cus);
-// Tuning hook: size from which plain products use the 256 tile, and the CU
-// count of the tail rule (0: the device's).
-void gemm_set_big_tiles(int64_t min_n, int tail_cus);
+// Default size from which products use the 256 tile (a matrix of this order
+// first fills one whole round of 256 tiles on 256 CUs; see gemm_use_big).
+constexpr int64_t kBigMinDefault = 5633;
+// Tuning hooks: size from which products use the 256 tile (0 restores
+// kBigMinDefault), and the CU count of the tail rule (0: the device's).
+void gemm_set_big_min(int64_t min_n);
+int64_t gemm_big_min();
+void gemm_set_tail_cus(int tail_cus);
 // Whether split products of matrices that use the 256 tile use it too (else
 // they run the 128-tile list). Tuning hook: mask, bit 0 FP16/BF16 pairs, bit 1
 // FP8 pairs.

@@ -26,6 +26,8 @@ namespace psd {
 namespace {
 
 constexpr int kDefaultLanczos = 20;
+// Caller-I/O tables kept per multi-matrix plan (see Plan::IoSlot).
+constexpr int kIoRing = 8;
 constexpr uint64_t kLanczosSeed = 0;
 // FP16_SPLIT default: hi + lo products in stages 2 and 3, the stages whose
 // FP16 rounding contributes most to the error (measured at n = 10^4 on GOE
@@ -34,6 +36,16 @@ constexpr uint64_t kLanczosSeed = 0;
 // product stays plain.
 constexpr uint32_t kDefaultSplitMask = 0x6;
 constexpr int kDefaultSplitFinal = 0;
+// BF16 default: BF16 hi + lo products in stages 1-4. BF16 keeps 8 significant
+// bits (unit roundoff 2^-9), so plain BF16 storage at every stage measures
+// 1.1e-2 (n = 10^4) to 1.6e-2 (n = 1024) against the FP64 composite
+// polynomial; a rounding simulation over split masks (n = 64..2048, GOE and
+// clustered spectra) gives 6-8e-3 for stages 2-3, 6.2-12.5e-3 for 2-4 and
+// 3.2-3.4e-3 for 1-4, the cheapest mask under the 5e-3 half-precision target.
+constexpr uint32_t kDefaultSplitMaskBf16 = 0xF;
+// split_mask bit 31: take bits 0..30 as given, even when they are all zero
+// (a zero mask otherwise selects the mode's default).
+constexpr uint32_t kExplicitMask = 0x80000000u;
 
 struct StagePlan {
     int T = 0;
@@ -105,8 +117,11 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
         p.b[t] = tab[t].b * s;
         p.c[t] = tab[t].c * s;
     }
-    if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT) {
-        p.split_mask = (o.split_mask ? o.split_mask : kDefaultSplitMask) & ((1u << T) - 1);
+    if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT || o.mode == PSDPROJ_MODE_BF16) {
+        const uint32_t def = o.mode == PSDPROJ_MODE_BF16 ? kDefaultSplitMaskBf16 : kDefaultSplitMask;
+        const uint32_t m = (o.split_mask & kExplicitMask) ? (o.split_mask & ~kExplicitMask)
+                                                          : (o.split_mask ? o.split_mask : def);
+        p.split_mask = m & ((1u << T) - 1);
         p.split_final = o.split_final < 0 ? kDefaultSplitFinal : o.split_final != 0;
     } else if (o.mode == PSDPROJ_MODE_FP32_EMU) {
         // every product on hi + lo FP16 pairs: ~22-bit operands, FP32 accumulation
@@ -181,16 +196,27 @@ struct Plan {
     std::vector<MatLayout> mats;
     // arena the device tables were built for
     void *base = nullptr;
-    // pinned staging of the per-call I/O table (multi-matrix plans), and the
-    // table last uploaded to the arena (io_valid: it is still there)
-    IoArg *io_host = nullptr;
-    hipEvent_t io_done = nullptr;
-    std::vector<IoArg> io_last;
-    bool io_valid = false;
+    // Caller-I/O tables of multi-matrix plans: a ring of kIoRing tables in the
+    // arena, each with its pinned staging copy and the event of its last
+    // upload. A call whose pointers match a resident table uses it as is (no
+    // upload). A table used by a call made while its stream was capturing is
+    // pinned: a captured graph reads it at every replay, so no later call
+    // overwrites it (until the plan is rebuilt or released).
+    struct IoSlot {
+        std::vector<IoArg> ios;
+        bool valid = false, pinned = false;
+        uint64_t used = 0;
+        IoArg *host = nullptr;
+        hipEvent_t done = nullptr;
+    };
+    IoSlot io_ring[kIoRing];
+    uint64_t io_clock = 0;
 
     ~Plan() {
-        if (io_done) (void)hipEventDestroy(io_done);
-        if (io_host) (void)hipHostFree(io_host);
+        for (IoSlot &r : io_ring) {
+            if (r.done) (void)hipEventDestroy(r.done);
+            if (r.host) (void)hipHostFree(r.host);
+        }
     }
     // rq: the stage plan of the request (mode, split choices)
     bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n) const {
@@ -224,7 +250,7 @@ void layout_plan(Plan &P) {
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     P.off_desc = take(sizeof(MatDesc) * M);
-    P.off_io = take(sizeof(IoArg) * M);
+    P.off_io = take(sizeof(IoArg) * M * kIoRing);
     P.off_wvec = take(sizeof(WorkItem) * (size_t)P.n_vec);
     P.off_wsymv = take(sizeof(WorkItem) * (size_t)P.n_symv);
     P.off_wcast = take(sizeof(WorkItem) * (size_t)P.n_cast);
@@ -241,7 +267,7 @@ void layout_plan(Plan &P) {
 // tables being replaced.
 int build_tables(Plan &P, void *base, hipStream_t s) {
     const size_t M = P.ns.size();
-    P.io_valid = false;
+    for (Plan::IoSlot &r : P.io_ring) r.valid = r.pinned = false;
     uint8_t *b = (uint8_t *)base;
     std::vector<MatDesc> desc(M);
     std::vector<WorkItem> wv, wt, wc;
@@ -312,9 +338,12 @@ int get_workspace(Pool &p, hipStream_t s, size_t bytes, void **out) {
     return PSDPROJ_OK;
 }
 
-__global__ void info_kernel(const MatDesc *D, psdproj_info *info, int stages) {
+// Numerical status of matrix blockIdx.x into the info buffer its I/O names.
+__global__ void info_kernel(const MatDesc *D, const IoArg *io_tab, IoArg io0, int stages) {
     if (threadIdx.x != 0) return;
-    const Scalars *s = D[0].scal;
+    psdproj_info *info = (psdproj_info *)io_of(io_tab, io0, blockIdx.x).info;
+    if (!info) return;
+    const Scalars *s = D[blockIdx.x].scal;
     info->lambda = s->lam;
     info->lanczos_lambda = s->lanczos_lam;
     info->sigma = s->sigma;
@@ -358,7 +387,7 @@ int gemm_class(bool split_operands, int epi) {
 
 // Enqueue the whole sequence for the plan's matrices. ios: host array of the
 // caller's I/O, one per matrix.
-int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, psdproj_info *info, bool bound_only) {
+int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bool want_info, bool bound_only) {
     uint8_t *b = (uint8_t *)P.base;
     const int M = (int)P.ns.size();
     BatchLaunch B;
@@ -373,38 +402,63 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
     if (M == 1) {
         B.io_tab = nullptr;
         B.io0 = ios[0];
-    } else if (P.io_valid && !memcmp(P.io_last.data(), ios, sizeof(IoArg) * M)) {
-        // the same buffers as the last call: the table in the arena is current,
-        // so the call is kernel launches only (and can be captured in a graph)
-        B.io_tab = (const IoArg *)(b + P.off_io);
     } else {
-        // A new table is uploaded through pinned staging with a host-side wait,
-        // which stream capture cannot record: capture only repeated calls.
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-            return PSDPROJ_ERR_UNSUPPORTED;
-        // per-call I/O table: pinned staging, reused once its last upload ran
-        if (!P.io_host) {
-            if (hipHostMalloc((void **)&P.io_host, sizeof(IoArg) * M, hipHostMallocDefault) != hipSuccess)
-                return PSDPROJ_ERR_NO_MEMORY;
-            if (hipEventCreateWithFlags(&P.io_done, hipEventDisableTiming) != hipSuccess) return PSDPROJ_ERR_HIP;
-        } else if (hipEventSynchronize(P.io_done) != hipSuccess) {
-            return PSDPROJ_ERR_HIP;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess) return PSDPROJ_ERR_HIP;
+        const bool capturing = cs != hipStreamCaptureStatusNone;
+        int hit = -1;
+        for (int k = 0; k < kIoRing; ++k) {
+            const Plan::IoSlot &r = P.io_ring[k];
+            if (r.valid && !memcmp(r.ios.data(), ios, sizeof(IoArg) * M)) hit = k;
         }
-        memcpy(P.io_host, ios, sizeof(IoArg) * M);
-        IoArg *io_dev = (IoArg *)(b + P.off_io);
-        P.io_valid = false;
-        if (hipMemcpyAsync(io_dev, P.io_host, sizeof(IoArg) * M, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipEventRecord(P.io_done, s) != hipSuccess)
-            return PSDPROJ_ERR_HIP;
-        P.io_last.assign(ios, ios + M);
-        P.io_valid = true;
-        B.io_tab = io_dev;
+        if (hit < 0) {
+            // A new table is uploaded through pinned staging with a host-side
+            // wait, which stream capture cannot record: capture only calls
+            // whose pointers were used before. The table replaced is the least
+            // recently used one that no capture holds.
+            if (capturing) return PSDPROJ_ERR_UNSUPPORTED;
+            for (int k = 0; k < kIoRing; ++k) {
+                const Plan::IoSlot &r = P.io_ring[k];
+                if (r.pinned) continue;
+                if (hit < 0) {
+                    hit = k;
+                    continue;
+                }
+                const Plan::IoSlot &h = P.io_ring[hit];
+                if (h.valid && (!r.valid || r.used < h.used)) hit = k;
+            }
+            if (hit < 0) return PSDPROJ_ERR_UNSUPPORTED;  // every table is held by a captured graph
+            Plan::IoSlot &r = P.io_ring[hit];
+            if (!r.host) {
+                if (hipHostMalloc((void **)&r.host, sizeof(IoArg) * M, hipHostMallocDefault) != hipSuccess) {
+                    r.host = nullptr;
+                    return PSDPROJ_ERR_NO_MEMORY;
+                }
+                if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess) {
+                    r.done = nullptr;
+                    return PSDPROJ_ERR_HIP;
+                }
+            } else if (hipEventSynchronize(r.done) != hipSuccess) {  // staging reused once its upload ran
+                return PSDPROJ_ERR_HIP;
+            }
+            memcpy(r.host, ios, sizeof(IoArg) * M);
+            r.valid = false;
+            IoArg *io_dev = (IoArg *)(b + P.off_io) + (size_t)hit * M;
+            if (hipMemcpyAsync(io_dev, r.host, sizeof(IoArg) * M, hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipEventRecord(r.done, s) != hipSuccess)
+                return PSDPROJ_ERR_HIP;
+            r.ios.assign(ios, ios + M);
+            r.valid = true;
+        }
+        Plan::IoSlot &r = P.io_ring[hit];
+        r.used = ++P.io_clock;
+        if (capturing) r.pinned = true;
+        B.io_tab = (const IoArg *)(b + P.off_io) + (size_t)hit * M;
     }
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (bound_only) {
-        if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, B.desc, info, 0);
+        if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, 0);
         return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
     }
     const StagePlan &p = P.sp;
@@ -483,7 +537,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, ps
     // out = (X + lam X0 X_T) / 2
     e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL, 0);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (info) hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, s, B.desc, info, p.T);
+    if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, p.T);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
 }
 
@@ -550,12 +604,12 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     Plan *P = nullptr;
     const int st = prepare(o, steps, std::vector<int64_t>{n}, s, &P);
     if (st != PSDPROJ_OK) return st;
-    const IoArg io{X, out, ld};
-    return run_plan(*P, &io, o, s, info, bound_only);
+    const IoArg io{X, out, ld, info};
+    return run_plan(*P, &io, o, s, info != nullptr, bound_only);
 }
 
 int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_t *ld, const float *const *X,
-                float *const *out, hipStream_t s) {
+                float *const *out, hipStream_t s, psdproj_info *info) {
     StagePlan tmp;
     if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
     if (count < 0 || (count > 0 && (!n || !ld || !X || !out))) return PSDPROJ_ERR_INVALID_ARG;
@@ -567,7 +621,7 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
         if (n[i] > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
         if (n[i] == 0) continue;
         ns.push_back(n[i]);
-        ios.push_back(IoArg{X[i], out[i], ld[i]});
+        ios.push_back(IoArg{X[i], out[i], ld[i], info ? (void *)(info + i) : nullptr});
     }
     if (ns.empty()) return PSDPROJ_OK;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
@@ -576,7 +630,7 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
     Plan *P = nullptr;
     const int st = prepare(o, steps, ns, s, &P);
     if (st != PSDPROJ_OK) return st;
-    return run_plan(*P, ios.data(), o, s, nullptr, false);
+    return run_plan(*P, ios.data(), o, s, info != nullptr, false);
 }
 
 psdproj_opts default_opts(int mode) {
@@ -680,7 +734,14 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
 int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld, const float *const *X, float *const *out,
                             int mode, psdproj_stream_t stream) {
     const psdproj_opts o = default_opts(mode);
-    return run_batched(o, count, n, ld, X, out, (hipStream_t)stream);
+    return run_batched(o, count, n, ld, X, out, (hipStream_t)stream, nullptr);
+}
+
+int psdproj_project_batched_ex(const psdproj_opts *opts, int count, const int64_t *n, const int64_t *ld,
+                               const float *const *X, float *const *out, psdproj_stream_t stream,
+                               psdproj_info *info_dev) {
+    if (!opts) return PSDPROJ_ERR_INVALID_ARG;
+    return run_batched(*opts, count, n, ld, X, out, (hipStream_t)stream, info_dev);
 }
 
 size_t psdproj_workspace_bytes(int64_t n, int mode) { return workspace_bytes_for(n, mode); }
@@ -723,9 +784,6 @@ int psdproj_release(void) {
     g_sg.clear();
     return PSDPROJ_OK;
 }
-
-static int64_t g_big_min_hook = 5633;
-static int g_tail_cus_hook = 0;
 
 int psdproj_gemm_timing_start(void) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -774,16 +832,14 @@ int psdproj_tune(const char *key, int64_t value) {
         for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
         return PSDPROJ_OK;
     }
-    if (!strcmp(key, "gemm_big_min")) {  // plain products of n >= value use the 256 tile
-        if (value < 1) return PSDPROJ_ERR_INVALID_ARG;
-        gemm_set_big_tiles(value, g_tail_cus_hook);
-        g_big_min_hook = value;
+    if (!strcmp(key, "gemm_big_min")) {  // products of n >= value use the 256 tile (0: default)
+        if (value < 0) return PSDPROJ_ERR_INVALID_ARG;
+        gemm_set_big_min(value);
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_tail_cus")) {  // CU count of the tail rule (0: the device's)
         if (value < 0 || value > 65536) return PSDPROJ_ERR_INVALID_ARG;
-        g_tail_cus_hook = (int)value;
-        gemm_set_big_tiles(g_big_min_hook, g_tail_cus_hook);
+        gemm_set_tail_cus((int)value);
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_split_big")) {  // bit 0: FP16/BF16 pairs, bit 1: FP8 pairs on 256 tiles

@@ -50,6 +50,10 @@ struct Req {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    // numerical status of the running request: the device info record, and
+    // its nonfinite flag copied to pinned host memory before `done`
+    psdproj_info *info_dev = nullptr;
+    int32_t *nonfinite_host = nullptr;
     bool busy = false;
     uint64_t ticket = 0;
     size_t held = 0;        // workspace bytes this slot's pool holds
@@ -150,8 +154,14 @@ void psdproj_server::launch(int si, uint64_t ticket, std::unique_lock<std::mutex
         hipEvent_t ev = sl.done;
         lk.unlock();  // enqueueing ~160 launches takes a while; let clients submit
         const psdproj_opts o = psd::default_opts(mode);
-        int status = psd::run_projection(o, r.n, r.ld, r.X, r.out, st, nullptr, false);
-        if (status == PSDPROJ_OK && hipEventRecord(ev, st) != hipSuccess) status = PSDPROJ_ERR_HIP;
+        psdproj_info *info = slots[si].info_dev;
+        int32_t *flag = slots[si].nonfinite_host;
+        *flag = 0;
+        int status = psd::run_projection(o, r.n, r.ld, r.X, r.out, st, info, false);
+        if (status == PSDPROJ_OK &&
+            (hipMemcpyAsync(flag, &info->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+             hipEventRecord(ev, st) != hipSuccess))
+            status = PSDPROJ_ERR_HIP;
         const size_t held = psd::pool_held(st);
         lk.lock();
         Req &q2 = reqs[ticket];
@@ -179,6 +189,7 @@ void psdproj_server::poll_completions() {
             const hipError_t e = hipEventQuery(sl.done);
             if (e == hipErrorNotReady) continue;
             if (e != hipSuccess) status = PSDPROJ_ERR_HIP;
+            else if (*sl.nonfinite_host) status = PSDPROJ_ERR_NONFINITE;  // out holds NaN
         }
         Req &q = reqs[sl.ticket];
         q.end_ns = now_ns();
@@ -245,10 +256,14 @@ int psdproj_serve_create(const psdproj_serve_config *cfg, psdproj_server **out) 
         if (hipGetDevice(&s->device) != hipSuccess) { delete s; return PSDPROJ_ERR_HIP; }
         for (Slot &sl : s->slots) {
             if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+                hipMalloc((void **)&sl.info_dev, sizeof(psdproj_info)) != hipSuccess ||
+                hipHostMalloc((void **)&sl.nonfinite_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
                 for (Slot &x : s->slots) {
                     if (x.done) (void)hipEventDestroy(x.done);
                     if (x.stream) (void)hipStreamDestroy(x.stream);
+                    if (x.info_dev) (void)hipFree(x.info_dev);
+                    if (x.nonfinite_host) (void)hipHostFree(x.nonfinite_host);
                 }
                 delete s;
                 return PSDPROJ_ERR_HIP;
@@ -398,6 +413,8 @@ int psdproj_serve_destroy(psdproj_server *s) {
             psd::pool_release(sl.stream);
             (void)hipEventDestroy(sl.done);
             (void)hipStreamDestroy(sl.stream);
+            (void)hipFree(sl.info_dev);
+            (void)hipHostFree(sl.nonfinite_host);
         }
     }
     delete s;

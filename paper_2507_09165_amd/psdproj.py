@@ -25,7 +25,7 @@ DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
           4: "HIP error", 5: "rejected", 6: "cancelled", 7: "timeout", 8: "not found",
-          9: "pending"}
+          9: "pending", 10: "non-finite input"}
 
 
 class PsdprojError(RuntimeError):
@@ -63,6 +63,9 @@ def lib() -> ctypes.CDLL:
     L.psdproj_spectral_bound.argtypes = [i64, i64, vp, c_int, vp, vp]
     L.psdproj_project_batched.argtypes = [c_int, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), c_int, vp]
+    L.psdproj_project_batched_ex.argtypes = [ctypes.POINTER(Opts), c_int, ctypes.POINTER(i64),
+                                             ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             vp, vp]
     L.psdproj_workspace_bytes.argtypes = [i64, c_int]
     L.psdproj_workspace_bytes.restype = ctypes.c_size_t
     L.psdproj_gemm_count.argtypes = [ctypes.POINTER(Opts), c_int]
@@ -80,7 +83,8 @@ def lib() -> ctypes.CDLL:
     L.psdproj_gemm_timing_stop.argtypes = [ctypes.c_void_p, c_int]
     for name in ("psdproj_gemm_timing_start", "psdproj_gemm_timing_stop",
                  "psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
-                 "psdproj_project_batched", "psdproj_gemm_count", "psdproj_coefficients",
+                 "psdproj_project_batched", "psdproj_project_batched_ex", "psdproj_gemm_count",
+                 "psdproj_coefficients",
                  "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8"):
         getattr(L, name).restype = c_int
     _lib = L
@@ -118,9 +122,15 @@ def _check_matrix(X, name="X"):
     return X.shape[0], X.stride(0)
 
 
-def make_opts(mode="fp16", lanczos_steps=0, split_mask=0, split_final=-1, lambda_override=0.0,
+EXPLICIT_MASK = 0x80000000
+
+
+def make_opts(mode="fp16", lanczos_steps=0, split_mask=None, split_final=-1, lambda_override=0.0,
               force_bound_fallback=False) -> Opts:
-    return Opts(_mode(mode), int(lanczos_steps), int(split_mask), int(split_final),
+    """split_mask None selects the mode's default split stages; an integer
+    (0 included) is taken as given (the library's explicit-mask bit)."""
+    mask = 0 if split_mask is None else (int(split_mask) | EXPLICIT_MASK)
+    return Opts(_mode(mode), int(lanczos_steps), mask, int(split_final),
                 float(lambda_override), int(bool(force_bound_fallback)))
 
 
@@ -168,10 +178,7 @@ def spectral_bound(X, lanczos_steps=20, stream=None) -> dict:
     return read_info(info_t)
 
 
-def project_batched(Xs, outs=None, mode="bf16", stream=None):
-    import torch
-    if outs is None:
-        outs = [torch.empty_like(X) for X in Xs]
+def _batch_args(Xs, outs):
     cnt = len(Xs)
     ns = (ctypes.c_int64 * cnt)()
     lds = (ctypes.c_int64 * cnt)()
@@ -179,10 +186,42 @@ def project_batched(Xs, outs=None, mode="bf16", stream=None):
     op = (ctypes.c_void_p * cnt)()
     for i, (X, O) in enumerate(zip(Xs, outs)):
         n, ld = _check_matrix(X)
+        if _check_matrix(O, "out") != (n, ld):
+            raise ValueError("out must match X in shape and stride")
         ns[i], lds[i], xp[i], op[i] = n, ld, X.data_ptr(), O.data_ptr()
+    return cnt, ns, lds, xp, op
+
+
+def project_batched(Xs, outs=None, mode="bf16", stream=None):
+    import torch
+    if outs is None:
+        outs = [torch.empty_like(X) for X in Xs]
+    cnt, ns, lds, xp, op = _batch_args(Xs, outs)
     _check(lib().psdproj_project_batched(cnt, ns, lds, xp, op, _mode(mode), _stream(stream)),
            "psdproj_project_batched")
     return outs
+
+
+def project_batched_ex(Xs, outs=None, stream=None, info=True, **opts):
+    """Batched projection with options; returns (outs, info_tensor) with one
+    64-byte info record per matrix (``read_infos``)."""
+    import torch
+    if outs is None:
+        outs = [torch.empty_like(X) for X in Xs]
+    cnt, ns, lds, xp, op = _batch_args(Xs, outs)
+    o = make_opts(**opts)
+    info_t = None
+    if info and cnt:
+        info_t = torch.zeros(64 * cnt, dtype=torch.uint8, device=Xs[0].device)
+    _check(lib().psdproj_project_batched_ex(ctypes.byref(o), cnt, ns, lds, xp, op, _stream(stream),
+                                            _ptr(info_t)), "psdproj_project_batched_ex")
+    return outs, info_t
+
+
+def read_infos(info_t) -> list:
+    raw = info_t.cpu().numpy().tobytes()
+    recs = np.frombuffer(raw, dtype=INFO_DTYPE)
+    return [{k: r[k].item() for k in INFO_DTYPE.names} for r in recs]
 
 
 def workspace_bytes(n: int, mode="fp16") -> int:

@@ -37,19 +37,25 @@ def test_batched_mixed_sizes_equal_single(mode):
 
 
 def test_batched_blocks_match_oracle():
+    """The batched workload (256 GOE blocks, n log-uniform in [32, 1024],
+    seed 7, BF16 with its default split): every block against the FP64 oracle
+    with the bound the batch computed for it, at the half-precision target."""
     import torch
-    sizes = inputs.batch_sizes(256, 7)[:24]
+    sizes = inputs.batch_sizes(256, 7)
     blocks = inputs.batch_blocks(sizes, 7)
-    say("batched C4 subset", list(sizes))
+    say("batched C4, 256 blocks")
     Xs = [to_dev(B) for B in blocks]
-    outs = P.project_batched(Xs, mode="bf16")
-    infos = []
-    for X in Xs:  # bound of each block (same kernels as inside the batch)
-        infos.append(P.spectral_bound(X))
+    outs, info_t = P.project_batched_ex(Xs, mode="bf16")
     torch.cuda.synchronize()
-    for B, o, info in zip(blocks, outs, infos):
+    infos = P.read_infos(info_t)
+    worst = 0.0
+    for k, (B, o, info) in enumerate(zip(blocks, outs, infos)):
+        assert info["nonfinite"] == 0 and info["fallback"] == 0
         ref, _ = oracle.project_poly(B.astype(np.float64), "bf16", lam=info["lambda"])
-        assert rel_fro(o.cpu().numpy(), ref) < 3e-2
+        e = rel_fro(o.cpu().numpy(), ref)
+        worst = max(worst, e)
+        assert e <= 5e-3, (k, B.shape[0], e)
+    say(f"  worst block error {worst:.3e}")
 
 
 def test_batched_with_zero_sized_and_empty():
@@ -84,3 +90,23 @@ def test_served_results_equal_alone():
     assert st["completed"] == len(sizes)
     for i in range(len(sizes)):
         assert torch.equal(outs[i], alone[i]), sizes[i]
+
+
+def test_served_nonfinite_request_reports_status():
+    """A served request whose input holds a NaN completes with
+    PSDPROJ_ERR_NONFINITE (10) and a NaN output; a finite request served
+    beside it completes normally."""
+    import torch
+    Xb = inputs.goe(300, 41)
+    Xb[5, 9] = Xb[9, 5] = np.nan
+    Xbad, Xok = to_dev(Xb), to_dev(inputs.goe(300, 42))
+    obad, ook = torch.zeros_like(Xbad), torch.zeros_like(Xok)
+    ref = P.project(Xok, mode="fp8_fp16_split")
+    torch.cuda.synchronize()
+    with P.Server(slots=2) as s:
+        t1 = s.submit(X=Xbad, out=obad, target=1e-3, tag=1)
+        t2 = s.submit(X=Xok, out=ook, target=1e-3, tag=2)
+        r1, r2 = s.wait(t1, timeout_s=60), s.wait(t2, timeout_s=60)
+    assert r1["status"] == 10 and r2["status"] == 0
+    assert torch.isnan(obad).all()
+    assert torch.equal(ook, ref)

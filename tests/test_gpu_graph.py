@@ -76,3 +76,40 @@ def test_capture_refuses_new_batch_pointers():
     s.synchronize()
     for a, b in zip(outs, new_outs):
         assert torch.equal(a, b)
+
+
+def test_graph_survives_eager_calls_with_other_pointers():
+    """Ping-pong buffers: a graph captured on outputs A keeps writing A after
+    an eager call on the same stream wrote outputs B (other pointers, same
+    sizes): the eager call must not overwrite the table the graph reads."""
+    import torch
+    s = torch.cuda.Stream()
+    sizes = [64, 200, 333]
+    Xs = [to_dev(inputs.goe(n, 80 + n)) for n in sizes]
+    A = [torch.empty_like(X) for X in Xs]
+    B = [torch.empty_like(X) for X in Xs]
+    torch.cuda.synchronize()
+    P.project_batched(Xs, A, mode="fp16", stream=s)
+    s.synchronize()
+    ref = [a.clone() for a in A]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        P.project_batched(Xs, A, mode="fp16", stream=s)
+    for rep in range(3):
+        P.project_batched(Xs, B, mode="fp16", stream=s)  # eager, new pointers
+        s.synchronize()
+        for b, r in zip(B, ref):
+            assert torch.equal(b, r), rep
+        for b in B:
+            b.fill_(-7.0)
+        for a in A:
+            a.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        s.synchronize()
+        for a, r in zip(A, ref):
+            assert torch.equal(a, r), rep
+        for b in B:
+            assert torch.all(b == -7.0), rep
+    say("  graph kept its pointers across 3 eager calls with others")

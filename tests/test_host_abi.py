@@ -42,11 +42,14 @@ def test_library_coefficients_match_oracle(mode):
 
 def test_gemm_counts():
     assert P.gemm_count("fp16") == 22 == oracle.gemm_count("fp16")
-    assert P.gemm_count("bf16") == 22
+    # BF16: stages 1-4 split by default (X enters split from stage 1): 4 x 9 + 3 x 3 + 1
+    assert P.gemm_count("bf16") == 46
+    assert P.gemm_count("bf16", split_mask=0) == 22  # explicit: no split stage
     assert P.gemm_count("fp32") == 31 == oracle.gemm_count("fp32")
     assert P.gemm_count("fp32_emu") == 93  # 10 stages x 3 split products x 3 + 3
     # split products cost 2-3 GEMMs each: no split stages, split final only
-    assert P.gemm_count("fp16_split", split_mask=0, split_final=1) >= 22
+    assert P.gemm_count("fp16_split", split_mask=0, split_final=1) == 24  # X0 and X_T as pairs
+    assert P.gemm_count("fp16_split") == P.gemm_count("fp16_split", split_mask=0x6)  # default mask
     # a split product: 3 FP16 products with FP16 lo halves, 2 with FP8 pairs
     assert P.gemm_count("fp16_split", split_mask=0x6, split_final=0) == 22 + 6 * 2
     assert P.gemm_count("fp8_fp16_split", split_mask=0x6, split_final=0) == 22 + 6
@@ -92,7 +95,7 @@ def test_tuning_keys_validate_their_values():
     L = P.lib()
     t = lambda k, v: L.psdproj_tune(k.encode(), ctypes.c_int64(v))
     assert t("no_such_key", 1) != 0
-    for key, bad in (("gemm_tile", 64), ("gemm_big_min", 0), ("gemm_tail_cus", -1), ("gemm_split_big", 4),
+    for key, bad in (("gemm_tile", 64), ("gemm_big_min", -1), ("gemm_tail_cus", -1), ("gemm_split_big", 4),
                      ("gemm_ksplit", 0), ("gemm_block", 0), ("work_ld_pad", 100), ("work_ld_pad", -64)):
         assert t(key, bad) == 1, (key, bad)
     try:
@@ -100,6 +103,6 @@ def test_tuning_keys_validate_their_values():
                         ("gemm_split_big", 0), ("gemm_ksplit", 1), ("gemm_block", (4 << 8) | 4)):
             assert t(key, ok) == 0, (key, ok)
     finally:
-        for key, v in (("gemm_tile", 0), ("gemm_big_min", 5633), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
+        for key, v in (("gemm_tile", 0), ("gemm_big_min", 0), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
                        ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4)):
             assert t(key, v) == 0
