@@ -13,9 +13,6 @@ signs):
 * ``goe``                X = (G + G^T) / sqrt(2 n), G Gaussian (semicircle on [-2, 2]).
 * ``clustered``          20% of the eigenvalues in [-1e-3, 1e-3], 80% in [-1, 1].
 * ``lowrank_noise``      W W^T / n + sqrt(1e-2) (H + H^T) / sqrt(2 n), rank 500.
-* ``householder_spectrum`` X = Q diag(lam) Q^T with Q a product of k random
-                         Householder reflectors, so that exact references can
-                         be sampled column by column at any n.
 * ``batch_sizes``        256 block sizes, log-uniform in [32, 1024].
 * ``serving_trace``      Poisson arrivals, log-uniform sizes, ADMM-like drift.
 """
@@ -71,39 +68,6 @@ def lowrank_noise(n: int, seed_w: int, seed_h: int, rank: int = 500, noise_var: 
     H = _rng(seed_h).standard_normal((n, n))
     X = (W @ W.T) / n + np.sqrt(noise_var) * (H + H.T) / np.sqrt(2.0 * n)
     return X.astype(np.float32)
-
-
-def householder_vectors(n: int, k: int, seed: int) -> np.ndarray:
-    U = _rng(seed).standard_normal((k, n))
-    U /= np.linalg.norm(U, axis=1, keepdims=True)
-    return U
-
-
-def apply_q(U: np.ndarray, Y: np.ndarray) -> np.ndarray:
-    """Q Y with Q = H_0 H_1 ... H_{k-1}, H_i = I - 2 u_i u_i^T (Y: n or n x m)."""
-    Y = np.array(Y, dtype=np.float64, copy=True)
-    for u in U[::-1]:
-        Y -= 2.0 * np.outer(u, u @ Y) if Y.ndim == 2 else 2.0 * u * (u @ Y)
-    return Y
-
-
-def apply_qt(U: np.ndarray, Y: np.ndarray) -> np.ndarray:
-    """Q^T Y = H_{k-1} ... H_0 Y."""
-    Y = np.array(Y, dtype=np.float64, copy=True)
-    for u in U:
-        Y -= 2.0 * np.outer(u, u @ Y) if Y.ndim == 2 else 2.0 * u * (u @ Y)
-    return Y
-
-
-def householder_spectrum(n: int, lam: np.ndarray, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
-    """X = Q diag(lam) Q^T (FP32) with Q a product of k Householder reflectors.
-    Returns (X32, U) where U holds the reflector vectors (rows)."""
-    U = householder_vectors(n, k, seed)
-    M = np.diag(np.asarray(lam, dtype=np.float64))
-    M = apply_q(U, M)            # Q diag(lam)
-    M = apply_q(U, M.T).T        # (Q (Q diag)^T)^T = Q diag Q^T
-    M = 0.5 * (M + M.T)
-    return M.astype(np.float32), U
 
 
 def batch_sizes(count: int = 256, seed: int = 7, lo: int = 32, hi: int = 1024) -> np.ndarray:
