@@ -13,6 +13,8 @@ from .psd import (  # noqa: F401
     gemm_count,
     jacobi_eig,
     lanczos_bound,
+    newton_schulz_stage,
+    NS_ITERS,
     project_exact,
     project_exact_eigh,
     project_poly,

@@ -22,6 +22,10 @@ Functions and the passages they follow:
                            x (1 + p(x)) / 2.
 * ``efloat``             — eq. (12), the maximum error over all float32 values
                            in [-1, 1].
+* ``newton_schulz_stage``— the cubic Newton-Schulz step of the baseline in
+                           Section 4.1 ("Benchmark methods and metrics"); the
+                           ``ns_fp16`` / ``ns_fp32`` modes of ``project_poly``
+                           run 10 / 15 of them in place of the filter stages.
 
 Readings of the paper taken here (each also listed in the design notes):
 
@@ -183,8 +187,18 @@ def spectral_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, force_fallback: b
 # ---------------------------------------------------------------------------
 # Composite filter (Algorithm 2)
 # ---------------------------------------------------------------------------
+# Newton-Schulz baseline (Section 4.1, "Benchmark methods and metrics"): the
+# cubic sign iteration x <- (3 x - x^3) / 2, 10 iterations in half precision
+# (21 products) and 15 in single precision (31 products), on the same rescaled
+# input and with the same final step as Algorithm 2.
+NS_ITERS = {"ns_fp16": 10, "ns_fp32": 15}
+
+
 def stage_rows(mode: str) -> np.ndarray:
-    """(a, b, c) per stage with the stage rescale folded in, FP64."""
+    """(a, b, c) per stage with the stage rescale folded in, FP64. The
+    Newton-Schulz modes are the cubic (1.5, -0.5, 0) repeated."""
+    if mode in NS_ITERS:
+        return np.tile(np.array([[1.5, -0.5, 0.0]]), (NS_ITERS[mode], 1))
     return tables.runtime_table(tables.MODE_TABLE[mode])
 
 
@@ -208,6 +222,13 @@ def filter_stage(Y: np.ndarray, a: float, b: float, c: float) -> np.ndarray:
     A = Y @ Y
     B = b * A + c * (A @ A)
     return a * Y + Y @ B
+
+
+def newton_schulz_stage(Y: np.ndarray) -> np.ndarray:
+    """One cubic Newton-Schulz step Y' = (3 Y - Y^3) / 2 with two matrix
+    products: A = Y Y, Y' = 1.5 Y - 0.5 Y A."""
+    A = Y @ Y
+    return 1.5 * Y - 0.5 * (Y @ A)
 
 
 def final_combine(X0: np.ndarray, Y: np.ndarray, lam: float) -> np.ndarray:
@@ -237,14 +258,20 @@ def project_poly(X, mode: str = "fp16", lam: float | None = None,
         return np.zeros_like(Xs), info
     X0 = Xs / lam
     Y = X0
-    for a, b, c in stage_rows(mode):
-        Y = filter_stage(Y, a, b, c)
+    if mode in NS_ITERS:
+        for _ in range(NS_ITERS[mode]):
+            Y = newton_schulz_stage(Y)
+    else:
+        for a, b, c in stage_rows(mode):
+            Y = filter_stage(Y, a, b, c)
     return final_combine(X0, Y, lam), info
 
 
 def gemm_count(mode: str) -> int:
-    """3 products per odd quintic stage plus the final X0 X_T."""
-    return 3 * stage_rows(mode).shape[0] + 1
+    """3 products per odd quintic stage (2 per cubic Newton-Schulz step)
+    plus the final X0 X_T."""
+    per = 2 if mode in NS_ITERS else 3
+    return per * stage_rows(mode).shape[0] + 1
 
 
 # ---------------------------------------------------------------------------

@@ -338,3 +338,78 @@ def test_poly_relative_error_floor_matches_exact_arithmetic():
         P, _ = oracle.project_poly(X, mode)
         rel = np.linalg.norm(P - R) / np.linalg.norm(R)
         assert rel < cap, (mode, rel)
+
+
+# --------------------------------------------------------------------------
+# Newton-Schulz baseline (Section 4.1, "Benchmark methods and metrics")
+# --------------------------------------------------------------------------
+def test_ns_structure_matches_printed_product_counts():
+    """10 half-precision iterations give 21 products, 15 single-precision ones
+    31 (Section 4.1's list of compared methods)."""
+    assert oracle.NS_ITERS == {"ns_fp16": 10, "ns_fp32": 15}
+    assert oracle.gemm_count("ns_fp16") == 21
+    assert oracle.gemm_count("ns_fp32") == 31
+
+
+def _ns_by_error_recursion(x, iters):
+    """The cubic sign iteration written in its error variable: with
+    e = 1 - |x|, one step gives e' = e^2 (3 - e) / 2 (since
+    1 - (3y - y^3)/2 = (1 - y)^2 (y + 2) / 2 and y + 2 = 3 - e); odd in x."""
+    x = np.asarray(x, dtype=np.float64)
+    e = 1.0 - np.abs(x)
+    for _ in range(iters):
+        e = e * e * (3.0 - e) / 2.0
+    return np.sign(x) * (1.0 - e)
+
+
+def test_ns_scalar_equals_error_recursion():
+    x = np.concatenate([np.linspace(-1.0, 1.0, 2001), [1e-4, -3e-3, 0.999]])
+    for mode, k in oracle.NS_ITERS.items():
+        got = oracle.psd.composite_scalar(x, oracle.stage_rows(mode))
+        np.testing.assert_allclose(got, _ns_by_error_recursion(x, k), atol=1e-13)
+
+
+def test_ns_converges_to_sign_inside_sqrt3_only():
+    """The cubic iteration converges to sign(x) for 0 < |x| < sqrt(3); at
+    sqrt(3) < |x| < 2 one step flips the sign (it then converges to -sign(x)),
+    and beyond |f(x)| > sqrt(3) it diverges (f(3) = -9)."""
+    rows = np.tile(np.array([[1.5, -0.5, 0.0]]), (80, 1))
+    inside = np.array([1e-3, 0.3, 1.0, 1.5, 1.73, -0.02, -1.7])
+    np.testing.assert_allclose(oracle.psd.composite_scalar(inside, rows), np.sign(inside), atol=1e-12)
+    flipped = np.array([1.74, 1.9, -1.8])
+    np.testing.assert_allclose(oracle.psd.composite_scalar(flipped, rows), -np.sign(flipped), atol=1e-12)
+    assert oracle.psd.composite_scalar(np.array([3.0]), rows[:1])[0] == -9.0
+    with np.errstate(over="ignore", invalid="ignore"):
+        out = oracle.psd.composite_scalar(np.array([3.0, -3.0]), np.tile(rows[:1], (4, 1)))
+    assert np.all(~np.isfinite(out) | (np.abs(out) > 1e6))
+
+
+@pytest.mark.parametrize("mode", ["ns_fp16", "ns_fp32"])
+def test_ns_matrix_equals_spectral_form(mode):
+    """Projection by the Newton-Schulz baseline on X = Q diag(l) Q^T equals
+    Q diag(lam g(l / lam)) Q^T with g(x) = x (1 + s(x)) / 2 and s the
+    iteration evaluated through its error recursion."""
+    n = 40
+    Q = inputs.haar_orthogonal(n, 7)
+    lam = np.random.default_rng(8).uniform(-1.2, 1.1, n)
+    X = (Q * lam) @ Q.T
+    X = 0.5 * (X + X.T)
+    lt = 1.31
+    P, _ = oracle.project_poly(X, mode, lam=lt)
+    k = oracle.NS_ITERS[mode]
+    ref = oracle.project_spectral(Q, lam, lambda l: lt * 0.5 * (l / lt) * (1.0 + _ns_by_error_recursion(l / lt, k)))
+    np.testing.assert_allclose(P, ref, atol=1e-12)
+
+
+def test_ns_less_accurate_than_composite_on_dense_spectrum():
+    """With a fifth of the eigenvalues within 1e-3 of zero, the composite
+    filter is more accurate than Newton-Schulz with about as many products, in
+    both settings (Section 4.1, "Results"; in exact arithmetic here)."""
+    X = inputs.clustered(200, 3)[0].astype(np.float64)
+    ex = oracle.project_exact(X)
+    e = {}
+    for mode in ("fp16", "ns_fp16", "fp32", "ns_fp32"):
+        P, _ = oracle.project_poly(X, mode)
+        e[mode] = np.linalg.norm(P - ex) / np.linalg.norm(ex)
+    assert e["fp16"] < 1e-4 < e["ns_fp16"]
+    assert e["fp32"] < 1e-5 < e["ns_fp32"]
