@@ -5,6 +5,7 @@ the CPU-baseline leg of ``bench.py`` may import it. It shares no code with the
 HIP library (``paper_2507_09165_amd``), and the library never imports it.
 """
 from .psd import (  # noqa: F401
+    deflation_pairs,
     efloat,
     efloat_rows,
     filter_stage,
@@ -13,10 +14,12 @@ from .psd import (  # noqa: F401
     gemm_count,
     jacobi_eig,
     lanczos_bound,
+    lanczos_run,
     newton_schulz_stage,
     NS_ITERS,
     project_exact,
     project_exact_eigh,
+    project_deflated,
     project_poly,
     project_spectral,
     spectral_bound,

@@ -22,6 +22,11 @@ Functions and the passages they follow:
                            x (1 + p(x)) / 2.
 * ``efloat``             — eq. (12), the maximum error over all float32 values
                            in [-1, 1].
+* ``project_deflated``   — deflation of converged dominant eigenpairs before
+                           filtering, the remedy Section 4.1 ("Results") and
+                           Section 5 propose for spectra with a few dominant
+                           eigenvalues (our reading: Rayleigh-Ritz pairs of X
+                           in the bound's Krylov basis, gated by residual).
 * ``newton_schulz_stage``— the cubic Newton-Schulz step of the baseline in
                            Section 4.1 ("Benchmark methods and metrics"); the
                            ``ns_fp16`` / ``ns_fp32`` modes of ``project_poly``
@@ -116,12 +121,12 @@ def start_vector(n: int, seed: int = LANCZOS_SEED) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Spectral bound (Theorem 2 + Lanczos on X^2)
 # ---------------------------------------------------------------------------
-def lanczos_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZOS_SEED):
-    """Largest Ritz pair (sigma, q) of ``steps`` Lanczos steps on A = X^2
-    (A applied as X (X v), never formed), then the bound
-    lambda = sqrt(sigma + ||A q - sigma q||_2) of Theorem 2.
+def lanczos_run(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZOS_SEED):
+    """``steps`` Lanczos steps on A = X^2 (A applied as X (X v), never formed),
+    full reorthogonalisation by two classical Gram-Schmidt passes.
 
-    Returns dict(lam, sigma, r, k) with k the number of Lanczos steps taken."""
+    Returns (V, T) with V the n x k orthonormal Krylov basis and T its k x k
+    tridiagonal, k the number of steps taken (early stop on breakdown)."""
     n = Xs.shape[0]
     v = start_vector(n, seed)
     v = v / np.linalg.norm(v)
@@ -145,9 +150,19 @@ def lanczos_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZO
         V[:, j + 1] = w / b
     Tm = np.diag(np.array(alpha[:k])) + np.diag(np.array(beta[: k - 1]), 1) \
         + np.diag(np.array(beta[: k - 1]), -1)
+    return V[:, :k], Tm
+
+
+def lanczos_bound(Xs: np.ndarray, steps: int = LANCZOS_STEPS, seed: int = LANCZOS_SEED):
+    """Largest Ritz pair (sigma, q) of ``steps`` Lanczos steps on A = X^2, then
+    the bound lambda = sqrt(sigma + ||A q - sigma q||_2) of Theorem 2.
+
+    Returns dict(lam, sigma, r, k) with k the number of Lanczos steps taken."""
+    V, Tm = lanczos_run(Xs, steps, seed)
+    k = V.shape[1]
     theta, S = np.linalg.eigh(Tm)
     sigma = float(theta[-1])
-    q = V[:, :k] @ S[:, -1]
+    q = V @ S[:, -1]
     q = q / np.linalg.norm(q)
     res = Xs @ (Xs @ q) - sigma * q
     r = float(np.linalg.norm(res))
@@ -265,6 +280,65 @@ def project_poly(X, mode: str = "fp16", lam: float | None = None,
         for a, b, c in stage_rows(mode):
             Y = filter_stage(Y, a, b, c)
     return final_combine(X0, Y, lam), info
+
+
+# ---------------------------------------------------------------------------
+# Deflation of dominant eigenpairs before filtering (Section 4.1 "Results",
+# Section 5 "Limitations and future work")
+# ---------------------------------------------------------------------------
+DEFLATE_RTOL = 1e-8
+
+
+def deflation_pairs(Xs: np.ndarray, kmax: int, steps: int = LANCZOS_STEPS, rtol: float = DEFLATE_RTOL):
+    """Dominant eigenpairs of X for deflation, from the Krylov basis V of the
+    bound's Lanczos run on X^2: the Rayleigh-Ritz pairs of X itself in that
+    basis, (mu_i, z_i = V s_i) with V^T X V s_i = mu_i s_i, resolve the sign
+    that X^2 loses. Of the kmax pairs of largest |mu|, those whose residual
+    ||X z_i - mu_i z_i|| is at most rtol |mu_i| (converged, so that removing
+    them is exact to that level) are returned, largest |mu| first.
+
+    Returns (mu, Z, resid) with Z n x d (unit columns), d <= kmax."""
+    V, _ = lanczos_run(Xs, steps)
+    XV = Xs @ V
+    H = V.T @ XV
+    H = 0.5 * (H + H.T)
+    mu, S = np.linalg.eigh(H)
+    order = np.argsort(-np.abs(mu), kind="stable")[: max(0, int(kmax))]
+    keep_mu, keep_z, keep_r = [], [], []
+    for i in order:
+        z = V @ S[:, i]
+        nz = np.linalg.norm(z)
+        z = z / nz
+        r = float(np.linalg.norm(Xs @ z - mu[i] * z))
+        if r <= rtol * abs(mu[i]):
+            keep_mu.append(float(mu[i]))
+            keep_z.append(z)
+            keep_r.append(r)
+    Z = np.array(keep_z).T if keep_z else np.zeros((Xs.shape[0], 0))
+    return np.array(keep_mu), Z, np.array(keep_r)
+
+
+def project_deflated(X, mode: str = "fp16", kmax: int = 1, lam: float | None = None,
+                     steps: int = LANCZOS_STEPS):
+    """Projection with deflation: remove the converged dominant pairs,
+    X' = X - sum_i mu_i z_i z_i^T, project X' with Algorithm 2 (its own
+    spectral bound, or ``lam``), and add back the PSD part of what was
+    removed: P = P(X') + sum_i max(mu_i, 0) z_i z_i^T. For exact eigenpairs
+    this is Pi(X) up to the filter's error on X' (the z_i are eigenvectors
+    of X' with eigenvalue 0, and Pi acts on each eigenspace separately).
+
+    Returns (P, info) with info of the inner projection plus mu, Z."""
+    Xs = sym_from_upper(X)
+    if Xs.shape[0] == 0:
+        return Xs.copy(), {"lam": 0.0, "mu": np.zeros(0), "Z": np.zeros((0, 0))}
+    if not np.all(np.isfinite(Xs)):
+        raise ValueError("non-finite input")
+    mu, Z, r = deflation_pairs(Xs, kmax, steps)
+    Xd = Xs - (Z * mu) @ Z.T
+    P, info = project_poly(Xd, mode, lam=lam, steps=steps)
+    P = P + (Z * np.maximum(mu, 0.0)) @ Z.T
+    info = dict(info, mu=mu, Z=Z, resid=r)
+    return 0.5 * (P + P.T), info
 
 
 def gemm_count(mode: str) -> int:

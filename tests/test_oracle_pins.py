@@ -413,3 +413,59 @@ def test_ns_less_accurate_than_composite_on_dense_spectrum():
         e[mode] = np.linalg.norm(P - ex) / np.linalg.norm(ex)
     assert e["fp16"] < 1e-4 < e["ns_fp16"]
     assert e["fp32"] < 1e-5 < e["ns_fp32"]
+
+
+# --------------------------------------------------------------------------
+# Deflation of dominant eigenpairs (Section 4.1 "Results"; Section 5)
+# --------------------------------------------------------------------------
+def _dominant(n, seed, top):
+    Q = inputs.haar_orthogonal(n, seed)
+    lam = np.random.default_rng(seed + 1).uniform(-1.0, 1.0, n)
+    lam[: len(top)] = top
+    X = (Q * lam) @ Q.T
+    return 0.5 * (X + X.T), Q, lam
+
+
+def test_deflation_finds_the_dominant_pairs_with_sign():
+    X, Q, lam = _dominant(300, 11, [200.0, -60.0])
+    mu, Z, r = oracle.deflation_pairs(X, 4)
+    np.testing.assert_allclose(mu, [200.0, -60.0], rtol=1e-12)
+    for i in range(2):
+        assert abs(abs(Z[:, i] @ Q[:, i]) - 1.0) < 1e-12
+    assert np.all(r <= 1e-8 * np.abs(mu))
+
+
+def test_deflated_projection_spectral_identity():
+    """With the dominant pairs removed exactly, the result is ReLU on them and
+    the filter with the deflated matrix's own bound on the rest."""
+    X, Q, lam = _dominant(300, 11, [200.0, -60.0])
+    P, info = oracle.project_deflated(X, "fp16", kmax=2)
+    lt = info["lam"]
+    assert lt < 1.01  # the bound of the deflated matrix
+    f = lt * oracle.g_scalar(lam / lt, "fp16")
+    f[:2] = np.maximum(lam[:2], 0.0)
+    ref = oracle.project_spectral(Q, lam, lambda l: f)
+    np.testing.assert_allclose(P, ref, atol=1e-10)
+
+
+def test_deflation_gate_leaves_unconverged_spectra_alone():
+    X = inputs.goe(200, 2).astype(np.float64)
+    mu, Z, r = oracle.deflation_pairs(X, 4)
+    assert mu.size == 0
+    P0, _ = oracle.project_poly(X, "fp16")
+    P1, _ = oracle.project_deflated(X, "fp16", kmax=4)
+    np.testing.assert_array_equal(P0, P1)
+
+
+def test_deflation_fixes_one_dominant_eigenvalue():
+    """One eigenvalue 1000x the rest: undeflated, the rest of the spectrum is
+    scaled below the filter's resolved interval; deflated, it is filtered at
+    the paper's half-precision accuracy."""
+    X, Q, lam = _dominant(400, 11, [1000.0])
+    ex = oracle.project_exact_eigh(X)
+    rest = ex - 1000.0 * np.outer(Q[:, 0], Q[:, 0])
+    e = []
+    for k in (0, 1):
+        P, _ = oracle.project_deflated(X, "fp16", kmax=k)
+        e.append(np.linalg.norm(P - ex) / np.linalg.norm(rest))
+    assert e[0] > 1e-2 and e[1] < 1e-4
