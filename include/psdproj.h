@@ -54,7 +54,9 @@ typedef enum {
     PSDPROJ_ERR_TIMEOUT = 7,
     PSDPROJ_ERR_NOT_FOUND = 8,
     PSDPROJ_ERR_PENDING = 9,
-    PSDPROJ_ERR_NONFINITE = 10 /* served request whose input held Inf/NaN */
+    PSDPROJ_ERR_NONFINITE = 10, /* served request whose input held Inf/NaN */
+    PSDPROJ_ERR_TOO_LARGE = 11  /* psdproj_project_noalloc: the workspace would not
+                                   fit in PSDPROJ_NOALLOC_SCRATCH_BYTES */
 } psdproj_status;
 
 /* Compute precision of the filter products. Storage of X and out is FP32. */
@@ -119,6 +121,29 @@ int psdproj_project(int64_t n, int64_t ld, const float *X, float *out, int mode,
  * receives the numerical status once the stream reaches the end of the call. */
 int psdproj_project_ex(const psdproj_opts *opts, int64_t n, int64_t ld, const float *X,
                        float *out, psdproj_stream_t stream, psdproj_info *info_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * psdproj_project_ex with the workspace in a fixed library-owned device array
+ * of PSDPROJ_NOALLOC_SCRATCH_BYTES per GPU (held from the library's load until
+ * the process ends) instead of the pooled workspace; it calls no hipMalloc,
+ * hipFree or other allocating routine. The caller still supplies X, out and
+ * info_dev. Every matrix with n <= 2048 fits in every mode and option set;
+ * larger ones fit while psdproj_workspace_bytes(n, mode) (default options)
+ * stays within the limit. A call whose workspace would exceed it returns
+ * PSDPROJ_ERR_TOO_LARGE and queues nothing. Results are bitwise those of
+ * psdproj_project_ex with the same arguments.
+ * The array is shared by every call on one GPU, and its contents are those
+ * the last call left: calls that overlap on one GPU (queued on different
+ * streams without ordering between them) race and give wrong results. A
+ * call whose (n, mode, options) differ from the previous call's on that GPU
+ * waits for the device (another stream) or the stream before rewriting the
+ * array's tables. Such a call cannot be captured (PSDPROJ_ERR_UNSUPPORTED
+ * while capturing); a call with the previous call's shape only launches
+ * kernels. */
+#define PSDPROJ_NOALLOC_SCRATCH_BYTES ((size_t)80 << 20)
+int psdproj_project_noalloc(const psdproj_opts *opts, int64_t n, int64_t ld, const float *X,
+                            float *out, psdproj_stream_t stream, psdproj_info *info_dev);
 
 /* Only the spectral bound (steps 1-2 of Algorithm 2, Theorem 2): fills
  * info_dev (device memory, required) for the upper triangle of X. */

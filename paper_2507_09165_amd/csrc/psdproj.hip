@@ -22,6 +22,12 @@
 #include "gemm_sym.hpp"
 #include "runtime.hpp"
 
+// Workspace of psdproj_project_noalloc: one copy per device, held from the
+// library's load until the process ends. Host code must not use this name as
+// a device address (it names a host-side stand-in); it takes the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) uint8_t scratch[PSDPROJ_NOALLOC_SCRATCH_BYTES];
+
 namespace psd {
 namespace {
 
@@ -543,35 +549,43 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
 
 // Plan lookup/creation for (device, stream); builds tables when the shape or
 // the arena changed.
+// Rebuilding a plan, growing the workspace or uploading tables wait on the
+// host, which stream capture cannot record: they are refused while the stream
+// is capturing (queried only when one of them is due).
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// A laid-out plan (no device memory yet) for the call shape on device dev.
+std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int steps, const std::vector<int64_t> &ns,
+                               int dev) {
+    std::unique_ptr<Plan> P(new Plan());
+    P->mode = o.mode;
+    P->steps = steps;
+    P->sp = sp;
+    P->split_mask = sp.split_mask;
+    P->split_final = sp.split_final;
+    P->ns = ns;
+    P->tile_gen = gemm_tile_generation();
+    P->split_big = gemm_split_big(sp.dtype);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    P->cus = gemm_tail_cus(cus);
+    layout_plan(*P);
+    return P;
+}
+
 int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hipStream_t s, Plan **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     StagePlan sp;
     if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
     Pool &pool = g_pool[{dev, s}];
-    // Rebuilding a plan, growing the workspace or uploading tables wait on
-    // the host, which stream capture cannot record: refuse them while the
-    // stream is capturing (queried only when one of them is due).
-    auto capturing = [&]() {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
-    };
+    auto capturing = [&]() { return stream_capturing(s); };
     if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns)) {
         if (capturing()) return PSDPROJ_ERR_UNSUPPORTED;
-        std::unique_ptr<Plan> P(new Plan());
-        P->mode = o.mode;
-        P->steps = steps;
-        P->sp = sp;
-        P->split_mask = sp.split_mask;
-        P->split_final = sp.split_final;
-        P->ns = ns;
-        P->tile_gen = gemm_tile_generation();
-        P->split_big = gemm_split_big(sp.dtype);
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        P->cus = gemm_tail_cus(cus);
-        layout_plan(*P);
+        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, dev);
         if (pool.plan && hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
         pool.plan = std::move(P);
     }
@@ -588,10 +602,70 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
     return PSDPROJ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free projections: the arena is the fixed device array `scratch`
+// (file scope, above) instead of pooled hipMalloc memory. Each device has its
+// own copy of the array, at the address hipGetSymbolAddress returns once per
+// device, and one plan: every such call on a device shares the array, and a
+// call whose shape differs from the previous one rebuilds the tables in it.
+// Nothing in the arena has to start at zero (the kernels write every work
+// matrix, padding included, before reading it, and no kernel accumulates
+// into workspace memory across launches).
+struct ScratchPool {
+    uint8_t *ptr = nullptr;  // this device's copy of `scratch`
+    std::unique_ptr<Plan> plan;
+    hipStream_t last = nullptr;  // stream of the previous call
+};
+std::map<int, ScratchPool> g_scratch;  // per device, guarded by g_mu
+
+// Device address of this device's copy of `scratch` (the current device's;
+// called once per device, with that device current).
+int scratch_address(void **p) {
+    *p = nullptr;
+    if (hipGetSymbolAddress(p, HIP_SYMBOL(scratch)) != hipSuccess || !*p) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return PSDPROJ_ERR_HIP;
+    }
+    return PSDPROJ_OK;
+}
+
+int prepare_scratch(const psdproj_opts &o, int steps, int64_t n, hipStream_t s, Plan **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
+    StagePlan sp;
+    if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
+    ScratchPool &sc = g_scratch[dev];
+    if (!sc.ptr) {
+        void *p = nullptr;
+        const int st = scratch_address(&p);
+        if (st != PSDPROJ_OK) return st;
+        sc.ptr = (uint8_t *)p;
+    }
+    const std::vector<int64_t> ns{n};
+    if (!sc.plan || !sc.plan->same_key(o, sp, steps, ns)) {
+        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, dev);
+        if (P->total > (size_t)PSDPROJ_NOALLOC_SCRATCH_BYTES) return PSDPROJ_ERR_TOO_LARGE;
+        if (stream_capturing(s)) return PSDPROJ_ERR_UNSUPPORTED;
+        // The previous call may still read the tables being replaced: on
+        // another stream it is awaited here, on this one by build_tables.
+        if (sc.plan && sc.last != s && hipDeviceSynchronize() != hipSuccess) return PSDPROJ_ERR_HIP;
+        sc.plan = std::move(P);
+        const int bt = build_tables(*sc.plan, sc.ptr, s);
+        if (bt != PSDPROJ_OK) {
+            sc.plan.reset();
+            return bt;
+        }
+    }
+    sc.last = s;
+    *out = sc.plan.get();
+    return PSDPROJ_OK;
+}
+
 }  // namespace
 
 int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
-                   psdproj_info *info, bool bound_only) {
+                   psdproj_info *info, bool bound_only, bool no_alloc) {
     StagePlan tmp;
     if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
@@ -602,7 +676,7 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *P = nullptr;
-    const int st = prepare(o, steps, std::vector<int64_t>{n}, s, &P);
+    const int st = no_alloc ? prepare_scratch(o, steps, n, s, &P) : prepare(o, steps, std::vector<int64_t>{n}, s, &P);
     if (st != PSDPROJ_OK) return st;
     const IoArg io{X, out, ld, info};
     return run_plan(*P, &io, o, s, info != nullptr, bound_only);
@@ -714,13 +788,19 @@ extern "C" {
 
 int psdproj_project(int64_t n, int64_t ld, const float *X, float *out, int mode, psdproj_stream_t stream) {
     const psdproj_opts o = default_opts(mode);
-    return run_projection(o, n, ld, X, out, (hipStream_t)stream, nullptr, false);
+    return run_projection(o, n, ld, X, out, (hipStream_t)stream, nullptr, false, false);
 }
 
 int psdproj_project_ex(const psdproj_opts *opts, int64_t n, int64_t ld, const float *X, float *out,
                        psdproj_stream_t stream, psdproj_info *info_dev) {
     if (!opts) return PSDPROJ_ERR_INVALID_ARG;
-    return run_projection(*opts, n, ld, X, out, (hipStream_t)stream, info_dev, false);
+    return run_projection(*opts, n, ld, X, out, (hipStream_t)stream, info_dev, false, false);
+}
+
+int psdproj_project_noalloc(const psdproj_opts *opts, int64_t n, int64_t ld, const float *X, float *out,
+                            psdproj_stream_t stream, psdproj_info *info_dev) {
+    if (!opts) return PSDPROJ_ERR_INVALID_ARG;
+    return run_projection(*opts, n, ld, X, out, (hipStream_t)stream, info_dev, false, true);
 }
 
 int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_steps, psdproj_stream_t stream,
@@ -728,7 +808,7 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
     if (!info_dev) return PSDPROJ_ERR_INVALID_ARG;
     psdproj_opts o = default_opts(PSDPROJ_MODE_FP32);
     o.lanczos_steps = lanczos_steps;
-    return run_projection(o, n, ld, X, nullptr, (hipStream_t)stream, info_dev, true);
+    return run_projection(o, n, ld, X, nullptr, (hipStream_t)stream, info_dev, true, false);
 }
 
 int psdproj_project_batched(int count, const int64_t *n, const int64_t *ld, const float *const *X, float *const *out,
@@ -830,6 +910,7 @@ int psdproj_tune(const char *key, int64_t value) {
         if (hipDeviceSynchronize() != hipSuccess) return PSDPROJ_ERR_HIP;  // plans in flight
         g_ld_pad = value;
         for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
+        for (auto &kv : g_scratch) kv.second.plan.reset();
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_big_min")) {  // products of n >= value use the 256 tile (0: default)
@@ -873,6 +954,8 @@ const char *psdproj_status_string(int status) {
         case PSDPROJ_ERR_TIMEOUT: return "timeout";
         case PSDPROJ_ERR_NOT_FOUND: return "not found";
         case PSDPROJ_ERR_PENDING: return "pending";
+        case PSDPROJ_ERR_NONFINITE: return "non-finite input";
+        case PSDPROJ_ERR_TOO_LARGE: return "workspace exceeds the fixed scratch of the allocation-free entry point";
     }
     return "unknown status";
 }

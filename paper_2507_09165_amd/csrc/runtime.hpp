@@ -10,7 +10,7 @@ namespace psd {
 
 // Enqueue one projection (or only the bound) on stream s.
 int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
-                   psdproj_info *info, bool bound_only);
+                   psdproj_info *info, bool bound_only, bool no_alloc = false);
 psdproj_opts default_opts(int mode);
 // Workspace bytes a projection of size n in mode needs (0 for a bad mode).
 size_t workspace_bytes_for(int64_t n, int mode);

@@ -25,7 +25,7 @@ DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
           4: "HIP error", 5: "rejected", 6: "cancelled", 7: "timeout", 8: "not found",
-          9: "pending", 10: "non-finite input"}
+          9: "pending", 10: "non-finite input", 11: "exceeds the fixed scratch"}
 
 
 class PsdprojError(RuntimeError):
@@ -60,6 +60,7 @@ def lib() -> ctypes.CDLL:
     i64, vp, c_int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
     L.psdproj_project.argtypes = [i64, i64, vp, vp, c_int, vp]
     L.psdproj_project_ex.argtypes = [ctypes.POINTER(Opts), i64, i64, vp, vp, vp, vp]
+    L.psdproj_project_noalloc.argtypes = [ctypes.POINTER(Opts), i64, i64, vp, vp, vp, vp]
     L.psdproj_spectral_bound.argtypes = [i64, i64, vp, c_int, vp, vp]
     L.psdproj_project_batched.argtypes = [c_int, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), c_int, vp]
@@ -82,7 +83,8 @@ def lib() -> ctypes.CDLL:
     L.psdproj_gemm_timing_start.argtypes = []
     L.psdproj_gemm_timing_stop.argtypes = [ctypes.c_void_p, c_int]
     for name in ("psdproj_gemm_timing_start", "psdproj_gemm_timing_stop",
-                 "psdproj_project", "psdproj_project_ex", "psdproj_spectral_bound",
+                 "psdproj_project", "psdproj_project_ex", "psdproj_project_noalloc",
+                 "psdproj_spectral_bound",
                  "psdproj_project_batched", "psdproj_project_batched_ex", "psdproj_gemm_count",
                  "psdproj_coefficients",
                  "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8"):
@@ -160,6 +162,22 @@ def project_ex(X, out=None, stream=None, info=True, **opts):
     _check(lib().psdproj_project_ex(ctypes.byref(o), n, ld, _ptr(X), _ptr(out), _stream(stream),
                                     _ptr(info_t)), "psdproj_project_ex")
     return out, info_t
+
+
+def project_noalloc(X, out, info_t=None, stream=None, **opts):
+    """psdproj_project_noalloc: the projection with its workspace in the
+    library's fixed device array (no device allocation by the library). out
+    (and info_t, 64 bytes of device memory, if given) are the caller's."""
+    n, ld = _check_matrix(X)
+    if _check_matrix(out, "out") != (n, ld):
+        raise ValueError("out must match X in shape and stride")
+    o = make_opts(**opts)
+    _check(lib().psdproj_project_noalloc(ctypes.byref(o), n, ld, _ptr(X), _ptr(out), _stream(stream),
+                                         _ptr(info_t)), "psdproj_project_noalloc")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 80 << 20  # PSDPROJ_NOALLOC_SCRATCH_BYTES
 
 
 def read_info(info_t) -> dict:

@@ -106,3 +106,26 @@ def test_tuning_keys_validate_their_values():
         for key, v in (("gemm_tile", 0), ("gemm_big_min", 0), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
                        ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4)):
             assert t(key, v) == 0
+
+
+def test_noalloc_scratch_holds_n2048_in_every_mode():
+    """The allocation-free entry point's fixed array (its size as the header
+    defines it) holds the workspace of every n <= 2048 in every mode."""
+    txt = open(os.path.join(ROOT, "include", "psdproj.h")).read()
+    m = re.search(r"#define PSDPROJ_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m, "scratch size define"
+    limit = int(m.group(1)) << int(m.group(2))
+    assert limit == P.NOALLOC_SCRATCH_BYTES
+    for mode in P.MODES:
+        assert P.workspace_bytes(2048, mode) <= limit, mode
+    assert P.workspace_bytes(4096, "fp16") > limit
+
+
+def test_noalloc_argument_errors_before_device_work():
+    L = P.lib()
+    o = P.make_opts(mode="fp16")
+    assert L.psdproj_project_noalloc(None, 4, 4, None, None, None, None) == 1
+    assert L.psdproj_project_noalloc(ctypes.byref(o), -1, 4, None, None, None, None) == 1
+    assert L.psdproj_project_noalloc(ctypes.byref(o), 4, 3, None, None, None, None) == 1
+    assert L.psdproj_project_noalloc(ctypes.byref(o), 0, 1, None, None, None, None) == 0
+    assert L.psdproj_status_string(11)

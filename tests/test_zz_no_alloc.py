@@ -1,0 +1,54 @@
+"""psdproj_project_noalloc (workspace in the library's fixed device array)
+against psdproj_project_ex on the same inputs: bitwise equal outputs and
+info records, on two calls in a row with the second one smaller, in a plain
+mode and a split mode; a matrix whose workspace exceeds the array is refused
+with PSDPROJ_ERR_TOO_LARGE and leaves out untouched."""
+import numpy as np
+import pytest
+
+from paper_2507_09165_amd import inputs
+from paper_2507_09165_amd import psdproj as P
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(X32, mode):
+    import torch
+    X = to_dev(X32)
+    ref, info_ref = P.project_ex(X, mode=mode)
+    out = torch.full_like(X, 7.0)
+    info = torch.zeros(64, dtype=torch.uint8, device=X.device)
+    P.project_noalloc(X, out, info, mode=mode)
+    torch.cuda.synchronize()
+    return ref, out, P.read_info(info_ref), P.read_info(info)
+
+
+@pytest.mark.parametrize("mode", ["fp16", "fp8_fp16_split", "fp32"])
+def test_noalloc_matches_project_ex(mode):
+    import torch
+    for n, seed in ((1500, 41), (333, 42)):   # second call smaller
+        say("noalloc", mode, n)
+        X32 = inputs.goe(n, seed)
+        ref, out, iref, iout = _pair(X32, mode)
+        assert torch.equal(out, ref), (mode, n)
+        assert iout == iref
+        assert iout["nonfinite"] == 0 and iout["stages"] > 0
+
+
+def test_noalloc_largest_size_and_refusal():
+    import torch
+    say("noalloc n=2048 bf16")
+    ref, out, iref, iout = _pair(inputs.goe(2048, 43), "bf16")
+    assert torch.equal(out, ref) and iout == iref
+    say("noalloc refusal n=4096")
+    X = to_dev(inputs.goe(4096, 44))
+    out = torch.full_like(X, 3.0)
+    with pytest.raises(P.PsdprojError) as e:
+        P.project_noalloc(X, out, mode="fp16")
+    assert e.value.status == 11
+    torch.cuda.synchronize()
+    assert bool(torch.all(out == 3.0))
+    # the array still serves a fitting call afterwards
+    ref, out, iref, iout = _pair(inputs.goe(700, 45), "fp16")
+    assert torch.equal(out, ref) and iout == iref
