@@ -72,13 +72,17 @@ typedef enum {
     PSDPROJ_MODE_FP32_EMU = 4,   /* Table 1 refined (T = 10), every product on FP16
                                     hi+lo pairs (FP32-level operands at the FP16
                                     MFMA rate), 93 product-equivalents              */
-    PSDPROJ_MODE_FP8_FP16_SPLIT = 5 /* Table 2 refined, FP16 bulk; the split products
+    PSDPROJ_MODE_FP8_FP16_SPLIT = 5, /* Table 2 refined, FP16 bulk; the split products
                                     of split_mask (and the final product if
                                     split_final) carry the correction as e4m3
                                     codes: L_hi R_hi on FP16 MFMAs plus both
                                     cross terms on one FP8 MFMA per 32 K, so a
                                     split product costs 2 product-equivalents
                                     instead of 3                                    */
+    PSDPROJ_MODE_NS_FP16 = 6,    /* Newton-Schulz baseline of Section 4.1: 10 cubic
+                                    steps (3x - x^3)/2 on FP16 MFMA, 21 products     */
+    PSDPROJ_MODE_NS_FP32 = 7     /* Newton-Schulz baseline: 15 cubic steps on FP32
+                                    MFMA, 31 products                                */
 } psdproj_mode;
 
 typedef struct {
@@ -94,6 +98,18 @@ typedef struct {
     double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */
     int force_bound_fallback; /* test hook: halve the Lanczos bound so that the
                                  guard must replace it by ||X||_F */
+    int deflate;              /* 0: off. k in 1..8: deflation of dominant
+                                 eigenpairs before filtering (Section 4.1
+                                 "Results", Section 5): of the k Rayleigh-Ritz
+                                 pairs (mu_i, z_i) of X with largest |mu_i| in
+                                 the Krylov basis of the bound's Lanczos run,
+                                 those with ||X z_i - mu_i z_i|| <= 1e-8 |mu_i|
+                                 are removed, X' = X - sum mu_i z_i z_i^T is
+                                 projected with its own bound, and
+                                 sum max(mu_i, 0) z_i z_i^T is added back.
+                                 Single projections only (batched calls return
+                                 PSDPROJ_ERR_UNSUPPORTED); the workspace gains an
+                                 ld x n FP32 copy. */
 } psdproj_opts;
 
 /* Written on the device by psdproj_project_ex / psdproj_spectral_bound. */
@@ -108,6 +124,8 @@ typedef struct {
     int32_t nonfinite;     /* input held Inf/NaN; out was set to NaN */
     int32_t fallback;      /* guard replaced an invalid Lanczos bound */
     int32_t stages;        /* filter stages applied */
+    int32_t deflated;      /* eigenpairs removed before filtering (opts.deflate) */
+    int32_t reserved;
 } psdproj_info;
 
 /* Project X onto the PSD cone (Algorithm 2) in the given psdproj_mode.
@@ -128,7 +146,8 @@ int psdproj_project_ex(const psdproj_opts *opts, int64_t n, int64_t ld, const fl
  * of PSDPROJ_NOALLOC_SCRATCH_BYTES per GPU (held from the library's load until
  * the process ends) instead of the pooled workspace; it calls no hipMalloc,
  * hipFree or other allocating routine. The caller still supplies X, out and
- * info_dev. Every matrix with n <= 2048 fits in every mode and option set;
+ * info_dev. Every matrix with n <= 2048 fits in every mode and option set
+ * without deflation (opts.deflate adds an ld x n FP32 copy to the workspace);
  * larger ones fit while psdproj_workspace_bytes(n, mode) (default options)
  * stays within the limit. A call whose workspace would exceed it returns
  * PSDPROJ_ERR_TOO_LARGE and queues nothing. Results are bitwise those of
@@ -243,13 +262,18 @@ typedef struct {
     int fake_executor;       /* 1: no GPU work; a request "runs" for a modelled
                                 time (tests of the scheduling logic on a CPU) */
     double fake_tflops;      /* fake executor speed (0 -> 500) */
+    int coalesce_max_n;      /* requests of order <= this (0 -> 1024; < 0: never)
+                                are admitted together with the queued requests of
+                                the same mode and order <= this, up to 32 per
+                                group, as one batched projection (results are
+                                bitwise those of the request alone) */
 } psdproj_serve_config;
 
 typedef struct {
     int64_t n, ld;
     const float *X;  /* device, upper triangle read */
     float *out;      /* device */
-    double target;   /* accuracy target when mode < 0: <= 1e-4 -> FP32,
+    double target;   /* accuracy target when mode < 0: <= 1e-4 -> FP32_EMU,
                         otherwise FP8_FP16_SPLIT */
     int mode;        /* psdproj_mode, or -1 to choose from target */
     uint64_t tag;    /* caller's tag, echoed in the result */

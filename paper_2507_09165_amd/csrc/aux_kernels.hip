@@ -327,6 +327,7 @@ __global__ __launch_bounds__(kVecThreads) void symv_reduce_kernel(const MatDesc 
         const double yk = ((ry[0][r] + ry[1][r]) + ry[2][r]) + ry[3][r];
         if (k < n) {
             y[k] = yk;
+            if (dst == DST_U && dm.U) dm.U[(int64_t)jstep * n + k] = yk;  // X v_j, kept for deflation
             if constexpr (NORMS) dm.colsq[k] = ((rc[0][r] + rc[1][r]) + rc[2][r]) + rc[3][r];
         }
         yb[r] = k < n ? yk : 0.0;

@@ -24,6 +24,22 @@ hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int fo
 // of code exponent e8), optionally split (hi + lo, or hi + FP8 pair).
 hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, int e8, hipStream_t s);
 
+// Deflation of dominant eigenpairs of one matrix (see deflate.hip). The
+// descriptor's U must have been filled by a spectral_bound run on io.X.
+struct DeflLaunch {
+    const MatDesc *desc = nullptr;     // device, one entry
+    const WorkItem *w_vec = nullptr;   // (0, block of 256 rows)
+    int64_t n_vec = 0;
+    const WorkItem *w_tri = nullptr;   // (0, 64 x 64 tile t = J (J + 1) / 2 + I) covering n
+    int64_t n_tri = 0;
+    IoArg io{};                        // caller's X (remove) or out (add back), ld
+};
+// Rayleigh-Ritz pairs of X in the Lanczos basis, the converged ones kept, and
+// the deflated copy X' = X - sum mu z z^T (upper triangle) written.
+hipError_t deflate_remove(const DeflLaunch &L, hipStream_t s);
+// out += sum max(mu, 0) z z^T (both triangles).
+hipError_t deflate_addback(const DeflLaunch &L, hipStream_t s);
+
 size_t lanczos_work_doubles(int64_t n, int steps);
 int64_t symv_tile_count(int64_t n);
 int64_t vec_block_count(int64_t n);

@@ -38,6 +38,13 @@ constexpr StageCoef kTildeHalf[7] = {
     {1.8804816691, -1.2583997294, 0.3779501813},
 };
 
+// Newton-Schulz baseline compared against in Section 4.1: the cubic sign
+// iteration x <- (3 x - x^3) / 2, 10 steps in half precision and 15 in single
+// precision (21 and 31 products with the final one), without stage rescale.
+constexpr StageCoef kNewtonSchulz = {1.5, -0.5, 0.0};
+constexpr int kNewtonSchulzHalf = 10;
+constexpr int kNewtonSchulzSingle = 15;
+
 // Number of stages followed by the 1/1.001 (single) or 1/1.01 (half) rescale.
 constexpr int kSingleRescaled = 8;
 constexpr double kSingleRescale = 1.0 / 1.001;

@@ -37,6 +37,27 @@ struct Scalars {
 };
 
 constexpr int kMaxLanczos = 32;
+constexpr int kMaxDeflate = 8;
+
+// Deflation state of one projection (opts.deflate > 0): candidate Rayleigh-
+// Ritz pairs of X in the Krylov basis of the bound's Lanczos run, the pairs
+// kept, and the buffers the deflation kernels use.
+struct DeflState {
+    int32_t kmax;                         // pairs requested (<= kMaxDeflate)
+    int32_t ncand;                        // candidates: min(kmax, Lanczos steps)
+    int32_t count;                        // pairs kept (converged)
+    int32_t pad_;
+    double cmu[kMaxDeflate];              // candidate eigenvalues of V^T X V, largest |mu| first
+    double cs[kMaxDeflate][kMaxLanczos];  // their eigenvectors in the Krylov basis
+    double mu[kMaxDeflate];               // kept pairs
+    double inv_nz[kMaxDeflate];           // 1 / ||V s|| of each kept pair
+    int32_t idx[kMaxDeflate];             // candidate index of each kept pair
+    double *Z;                            // n x kMaxDeflate: V s of every candidate
+    double *pH;                           // vector blocks x kMaxLanczos^2: partials of V^T (X V)
+    double *pz;                           // vector blocks x 2 kMaxDeflate: ||z||^2, ||X z - mu z||^2
+    float *Xd;                            // deflated copy of X (upper triangle), leading dimension ldd
+    int64_t ldd;
+};
 
 // Per-matrix descriptor of one projection's device workspace. A launch covers
 // every matrix of a batch: its work list maps each workgroup to a
@@ -51,6 +72,8 @@ struct MatDesc {
     void *hi[4], *lo[4];  // work slots: X0, then rotating A / B / X_t
     int32_t nbv;          // vector blocks: ceil(n / 256)
     int32_t pad_;
+    double *U;            // deflation only: X v_j of every Lanczos step (n x steps), else null
+    DeflState *defl;      // deflation only, else null
 };
 
 // Caller-owned input and output of one matrix: X upper triangle and out,

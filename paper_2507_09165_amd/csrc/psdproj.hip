@@ -55,6 +55,7 @@ constexpr uint32_t kExplicitMask = 0x80000000u;
 
 struct StagePlan {
     int T = 0;
+    bool cubic = false;  // Newton-Schulz steps a X + b X^3 (two products each)
     double a[16], b[16], c[16];
     int dtype = DT_F32;
     uint32_t split_mask = 0;
@@ -114,6 +115,19 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
             tab = kTildeSingle; T = 10; nres = kSingleRescaled; res = kSingleRescale; p.dtype = DT_F16; break;
         case PSDPROJ_MODE_FP8_FP16_SPLIT:
             tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_F16X8; break;
+        case PSDPROJ_MODE_NS_FP16:
+        case PSDPROJ_MODE_NS_FP32:
+            // Newton-Schulz baseline: x <- (3 x - x^3) / 2, no stage rescale
+            p.cubic = true;
+            p.T = o.mode == PSDPROJ_MODE_NS_FP16 ? kNewtonSchulzHalf : kNewtonSchulzSingle;
+            p.dtype = o.mode == PSDPROJ_MODE_NS_FP16 ? DT_F16 : DT_F32;
+            for (int t = 0; t < p.T; ++t) {
+                p.a[t] = kNewtonSchulz.a;
+                p.b[t] = kNewtonSchulz.b;
+                p.c[t] = kNewtonSchulz.c;
+            }
+            pair_exponents(p);
+            return true;
         default: return false;
     }
     p.T = T;
@@ -157,13 +171,16 @@ size_t align256(size_t b) { return (size_t)round_up((int64_t)b, 256); }
 // 10368) are left alone, which measured best.
 static int64_t g_ld_pad = 128;
 
-// One matrix's workspace inside the arena.
+// One matrix's workspace inside the arena. With deflation (defl_ld > 0) it
+// also holds the Lanczos products X V, the deflation state and buffers, and
+// the deflated FP32 copy of X (leading dimension defl_ld, the caller's).
 struct MatLayout {
     int64_t n, np, ldw;
     size_t off_scal, off_lz, off_mat, mat_bytes, total;
+    size_t off_U = 0, off_defl = 0, off_Z = 0, off_pH = 0, off_pz = 0, off_Xd = 0;
 };
 
-MatLayout mat_layout(int64_t n, const StagePlan &p, int steps) {
+MatLayout mat_layout(int64_t n, const StagePlan &p, int steps, int64_t defl_ld) {
     MatLayout L{};
     L.n = n;
     L.np = gemm_padded_size(n, plan_big(n, p));
@@ -175,6 +192,15 @@ MatLayout mat_layout(int64_t n, const StagePlan &p, int steps) {
     L.off_lz = take(sizeof(double) * lanczos_work_doubles(n, steps));
     L.mat_bytes = align256(elt_size(p.dtype) * (size_t)L.ldw * (size_t)L.np);
     L.off_mat = take(L.mat_bytes * 4 * (split ? 2 : 1));
+    if (defl_ld > 0) {
+        const size_t nbv = (size_t)vec_block_count(n);
+        L.off_U = take(sizeof(double) * (size_t)n * (size_t)steps);
+        L.off_defl = take(sizeof(DeflState));
+        L.off_Z = take(sizeof(double) * (size_t)n * kMaxDeflate);
+        L.off_pH = take(sizeof(double) * nbv * kMaxLanczos * kMaxLanczos);
+        L.off_pz = take(sizeof(double) * nbv * 2 * kMaxDeflate);
+        L.off_Xd = take(sizeof(float) * (size_t)defl_ld * (size_t)n);
+    }
     L.total = off;
     return L;
 }
@@ -182,6 +208,8 @@ MatLayout mat_layout(int64_t n, const StagePlan &p, int steps) {
 struct Plan {
     // key
     int mode = -1, steps = 0, split_final = 0;
+    int deflate = 0;       // pairs to deflate (single projections only)
+    int64_t defl_ld = 0;   // caller's leading dimension when deflating
     uint32_t split_mask = 0;
     std::vector<int64_t> ns;
     // layout
@@ -225,9 +253,10 @@ struct Plan {
         }
     }
     // rq: the stage plan of the request (mode, split choices)
-    bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n) const {
+    bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n,
+                  int64_t dld) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
-               ns == n && tile_gen == gemm_tile_generation();
+               ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld;
     }
 };
 
@@ -239,7 +268,7 @@ void layout_plan(Plan &P) {
     std::vector<int64_t> nps;
     std::vector<bool> big;
     for (int64_t n : P.ns) {
-        P.mats.push_back(mat_layout(n, P.sp, P.steps));
+        P.mats.push_back(mat_layout(n, P.sp, P.steps, P.deflate > 0 ? P.defl_ld : 0));
         const MatLayout &L = P.mats.back();
         P.n_vec += vec_block_count(n);
         P.n_symv += symv_tile_count(n);
@@ -277,6 +306,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     uint8_t *b = (uint8_t *)base;
     std::vector<MatDesc> desc(M);
     std::vector<WorkItem> wv, wt, wc;
+    std::vector<std::pair<DeflState *, DeflState>> defl_init;
     const bool split = P.sp.split_mask != 0 || P.sp.split_final;
     for (size_t m = 0; m < M; ++m) {
         const MatLayout &L = P.mats[m];
@@ -291,6 +321,19 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         for (int k = 0; k < 4; ++k) {
             d.hi[k] = mb + L.off_mat + (size_t)k * L.mat_bytes;
             d.lo[k] = split ? mb + L.off_mat + (size_t)(4 + k) * L.mat_bytes : nullptr;
+        }
+        if (P.deflate > 0) {
+            d.U = (double *)(mb + L.off_U);
+            d.defl = (DeflState *)(mb + L.off_defl);
+            DeflState ds;
+            memset(&ds, 0, sizeof(ds));
+            ds.kmax = P.deflate;
+            ds.Z = (double *)(mb + L.off_Z);
+            ds.pH = (double *)(mb + L.off_pH);
+            ds.pz = (double *)(mb + L.off_pz);
+            ds.Xd = (float *)(mb + L.off_Xd);
+            ds.ldd = P.defl_ld;
+            defl_init.push_back(std::make_pair(d.defl, ds));
         }
         for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
@@ -310,6 +353,9 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         !up(P.off_split, P.tiles.split.data(), sizeof(uint4) * P.tiles.split.size()) ||
         !up(P.off_fixup, P.tiles.fixup.data(), sizeof(uint4) * P.tiles.fixup.size()))
         return PSDPROJ_ERR_HIP;
+    for (const auto &di : defl_init)
+        if (hipMemcpy(di.first, &di.second, sizeof(DeflState), hipMemcpyHostToDevice) != hipSuccess)
+            return PSDPROJ_ERR_HIP;
     P.base = base;
     return PSDPROJ_OK;
 }
@@ -360,6 +406,8 @@ __global__ void info_kernel(const MatDesc *D, const IoArg *io_tab, IoArg io0, in
     info->nonfinite = s->nonfinite;
     info->fallback = s->fallback;
     info->stages = stages;
+    info->deflated = D[blockIdx.x].defl ? D[blockIdx.x].defl->count : 0;
+    info->reserved = 0;
 }
 
 // Optional event timing of the filter products (psdproj_gemm_timing_*): each
@@ -461,6 +509,21 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         if (capturing) r.pinned = true;
         B.io_tab = (const IoArg *)(b + P.off_io) + (size_t)hit * M;
     }
+    DeflLaunch DL;
+    if (P.deflate > 0 && !bound_only) {
+        // deflation (single projections): Lanczos on X recording X V, the
+        // converged dominant pairs removed into X', then the whole method on X'
+        DL.desc = B.desc;
+        DL.w_vec = B.w_vec;
+        DL.n_vec = B.n_vec;
+        DL.w_tri = B.w_cast;  // 64 x 64 triangle tiles of n_p >= n
+        DL.n_tri = B.n_cast;
+        DL.io = B.io0;
+        if (spectral_bound(B, P.steps, kLanczosSeed, 0, 0.0, s) != hipSuccess ||
+            deflate_remove(DL, s) != hipSuccess)
+            return PSDPROJ_ERR_HIP;
+        B.io0.X = (const float *)((uint8_t *)P.base + P.mat_off[0] + P.mats[0].off_Xd);
+    }
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (bound_only) {
@@ -525,6 +588,16 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         int pa = -1, pb = -1;
         for (int k = 1; k < 4; ++k)
             if (k != cur) { if (pa < 0) pa = k; else if (pb < 0) pb = k; }
+        if (p.cubic) {
+            // Newton-Schulz step: A = X X, X' = a X + b X A (no split stages)
+            e = product(cur, false, cur, false, -1, false, 0.f, 1.f, 0.f, pa, EPI_STORE, p.ea[t]);
+            if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+            e = product(cur, false, pa, false, cur, false, (float)p.a[t], (float)p.b[t], 0.f, pb, EPI_STORE,
+                        p.ex[t + 1]);
+            if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+            cur = pb;
+            continue;
+        }
         const bool xs = sp && cur_split;  // X enters as a pair only in a split stage
         const int st_epi = sp ? EPI_STORE_SPLIT : EPI_STORE;
         // A = X X
@@ -543,6 +616,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     // out = (X + lam X0 X_T) / 2
     e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL, 0);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+    if (P.deflate > 0 && deflate_addback(DL, s) != hipSuccess) return PSDPROJ_ERR_HIP;
     if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, p.T);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
 }
@@ -559,9 +633,11 @@ bool stream_capturing(hipStream_t s) {
 
 // A laid-out plan (no device memory yet) for the call shape on device dev.
 std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int steps, const std::vector<int64_t> &ns,
-                               int dev) {
+                               int64_t defl_ld, int dev) {
     std::unique_ptr<Plan> P(new Plan());
     P->mode = o.mode;
+    P->deflate = o.deflate;
+    P->defl_ld = defl_ld;
     P->steps = steps;
     P->sp = sp;
     P->split_mask = sp.split_mask;
@@ -576,16 +652,17 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     return P;
 }
 
-int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hipStream_t s, Plan **out) {
+int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, int64_t defl_ld, hipStream_t s,
+            Plan **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     StagePlan sp;
     if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
     Pool &pool = g_pool[{dev, s}];
     auto capturing = [&]() { return stream_capturing(s); };
-    if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns)) {
+    if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns, defl_ld)) {
         if (capturing()) return PSDPROJ_ERR_UNSUPPORTED;
-        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, dev);
+        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, defl_ld, dev);
         if (pool.plan && hipStreamSynchronize(s) != hipSuccess) return PSDPROJ_ERR_HIP;
         pool.plan = std::move(P);
     }
@@ -604,7 +681,7 @@ int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, hi
 
 // ---------------------------------------------------------------------------
 // Allocation-free projections: the arena is the fixed device array `scratch`
-// (file scope, above) instead of pooled hipMalloc memory. Each device has its
+// (file scope, below) instead of pooled hipMalloc memory. Each device has its
 // own copy of the array, at the address hipGetSymbolAddress returns once per
 // device, and one plan: every such call on a device shares the array, and a
 // call whose shape differs from the previous one rebuilds the tables in it.
@@ -630,7 +707,7 @@ int scratch_address(void **p) {
     return PSDPROJ_OK;
 }
 
-int prepare_scratch(const psdproj_opts &o, int steps, int64_t n, hipStream_t s, Plan **out) {
+int prepare_scratch(const psdproj_opts &o, int steps, int64_t n, int64_t defl_ld, hipStream_t s, Plan **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     StagePlan sp;
@@ -643,8 +720,8 @@ int prepare_scratch(const psdproj_opts &o, int steps, int64_t n, hipStream_t s, 
         sc.ptr = (uint8_t *)p;
     }
     const std::vector<int64_t> ns{n};
-    if (!sc.plan || !sc.plan->same_key(o, sp, steps, ns)) {
-        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, dev);
+    if (!sc.plan || !sc.plan->same_key(o, sp, steps, ns, defl_ld)) {
+        std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, defl_ld, dev);
         if (P->total > (size_t)PSDPROJ_NOALLOC_SCRATCH_BYTES) return PSDPROJ_ERR_TOO_LARGE;
         if (stream_capturing(s)) return PSDPROJ_ERR_UNSUPPORTED;
         // The previous call may still read the tables being replaced: on
@@ -674,9 +751,14 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     if (n == 0) return PSDPROJ_OK;
     if (!X || (!out && !bound_only)) return PSDPROJ_ERR_INVALID_ARG;
     if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
+    if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
+    psdproj_opts oo = o;
+    if (bound_only) oo.deflate = 0;
+    const int64_t defl_ld = oo.deflate > 0 ? ld : 0;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *P = nullptr;
-    const int st = no_alloc ? prepare_scratch(o, steps, n, s, &P) : prepare(o, steps, std::vector<int64_t>{n}, s, &P);
+    const int st = no_alloc ? prepare_scratch(oo, steps, n, defl_ld, s, &P)
+                            : prepare(oo, steps, std::vector<int64_t>{n}, defl_ld, s, &P);
     if (st != PSDPROJ_OK) return st;
     const IoArg io{X, out, ld, info};
     return run_plan(*P, &io, o, s, info != nullptr, bound_only);
@@ -697,12 +779,14 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
         ns.push_back(n[i]);
         ios.push_back(IoArg{X[i], out[i], ld[i], info ? (void *)(info + i) : nullptr});
     }
+    if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
+    if (o.deflate > 0) return PSDPROJ_ERR_UNSUPPORTED;  // deflation: single projections only
     if (ns.empty()) return PSDPROJ_OK;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
     if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *P = nullptr;
-    const int st = prepare(o, steps, ns, s, &P);
+    const int st = prepare(o, steps, ns, 0, s, &P);
     if (st != PSDPROJ_OK) return st;
     return run_plan(*P, ios.data(), o, s, info != nullptr, false);
 }
@@ -715,17 +799,22 @@ psdproj_opts default_opts(int mode) {
     return o;
 }
 
-size_t workspace_bytes_for(int64_t n, int mode) {
+size_t workspace_bytes_batch(const int64_t *ns, int count, int mode) {
     psdproj_opts o = default_opts(mode);
     StagePlan sp;
-    if (n <= 0 || !make_stage_plan(o, sp)) return 0;
+    if (count <= 0 || !make_stage_plan(o, sp)) return 0;
     Plan P;
     P.sp = sp;
     P.steps = kDefaultLanczos;
-    P.ns = {n};
+    for (int i = 0; i < count; ++i) {
+        if (ns[i] <= 0) return 0;
+        P.ns.push_back(ns[i]);
+    }
     layout_plan(P);
     return P.total;
 }
+
+size_t workspace_bytes_for(int64_t n, int mode) { return workspace_bytes_batch(&n, 1, mode); }
 
 size_t pool_held(hipStream_t s) {
     int dev = 0;
@@ -752,6 +841,7 @@ int gemm_count_for(const psdproj_opts &o) {
     if (!make_stage_plan(o, p)) return -1;
     // an FP16 pair product is 3 FP16 products; an FP8 pair product is one FP16
     // product plus one FP8 product of twice the K at twice the rate
+    if (p.cubic) return 2 * p.T + 1;
     const int pair = p.dtype == DT_F16X8 ? 2 : 3;
     int g = 0;
     bool cur_split = (p.split_mask & 1u) != 0;

@@ -11,7 +11,12 @@ namespace psd {
 // Enqueue one projection (or only the bound) on stream s.
 int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
                    psdproj_info *info, bool bound_only, bool no_alloc = false);
+// Enqueue one batched projection (per-matrix info at info[i], may be null).
+int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_t *ld, const float *const *X,
+                float *const *out, hipStream_t s, psdproj_info *info);
 psdproj_opts default_opts(int mode);
+// Workspace bytes of one batched call over the orders ns in mode.
+size_t workspace_bytes_batch(const int64_t *ns, int count, int mode);
 // Workspace bytes a projection of size n in mode needs (0 for a bad mode).
 size_t workspace_bytes_for(int64_t n, int mode);
 // Number of n_p x n_p products the projection runs.

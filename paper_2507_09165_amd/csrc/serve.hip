@@ -10,9 +10,17 @@
 // result and wakes waiters. Requests that arrive while others run are
 // admitted as slots free up, so their kernels overlap on the device.
 //
+// Coalescing: when a request of order <= coalesce_max_n is admitted, queued
+// requests of the same mode and no larger order join it (in arrival order, up
+// to kMaxGroup and within the budget) and the group runs as one batched
+// projection on the slot: one launch sequence covers every matrix, and each
+// result is bitwise the one the request would get alone (tile shapes and
+// reduction orders are per matrix).
+//
 // The fake executor (config.fake_executor) runs no GPU work: a request
 // "completes" after a modelled time, so the admission and bookkeeping logic
 // can be exercised on a machine without a GPU.
+#include <string.h>
 #include <time.h>
 
 #include <algorithm>
@@ -47,15 +55,17 @@ struct Req {
     bool finished = false;
 };
 
+constexpr int kMaxGroup = 32;  // requests in one coalesced launch
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    // numerical status of the running request: the device info record, and
-    // its nonfinite flag copied to pinned host memory before `done`
-    psdproj_info *info_dev = nullptr;
-    int32_t *nonfinite_host = nullptr;
+    // numerical status of the running requests: one device info record each,
+    // copied to pinned host memory before `done`
+    psdproj_info *info_dev = nullptr;   // kMaxGroup records
+    psdproj_info *info_host = nullptr;  // kMaxGroup records (pinned)
     bool busy = false;
-    uint64_t ticket = 0;
+    std::vector<uint64_t> group;  // tickets running on this slot
     size_t held = 0;        // workspace bytes this slot's pool holds
     int64_t fake_end = 0;
 };
@@ -91,13 +101,26 @@ struct psdproj_server {
     }
     void loop();
     int pick_slot(size_t ws);
-    void launch(int si, uint64_t ticket, std::unique_lock<std::mutex> &lk);
+    void launch(int si, const std::vector<uint64_t> &group, std::unique_lock<std::mutex> &lk);
     void poll_completions();
+    // Queued requests that may run with pending[idx] in one batched call.
+    std::vector<size_t> coalesce(size_t idx) const;
 };
 
 static int choose_mode(const psdproj_request &r) {
     if (r.mode >= 0) return r.mode;
-    return r.target <= 1e-4 ? PSDPROJ_MODE_FP32 : PSDPROJ_MODE_FP8_FP16_SPLIT;
+    return r.target <= 1e-4 ? PSDPROJ_MODE_FP32_EMU : PSDPROJ_MODE_FP8_FP16_SPLIT;
+}
+
+std::vector<size_t> psdproj_server::coalesce(size_t idx) const {
+    std::vector<size_t> pos{idx};
+    const Req &h = reqs.at(pending[idx]);
+    if (cfg.coalesce_max_n < 0 || h.r.n > cfg.coalesce_max_n || h.r.n == 0) return pos;
+    for (size_t k = idx + 1; k < pending.size() && (int)pos.size() < kMaxGroup; ++k) {
+        const Req &q = reqs.at(pending[k]);
+        if (q.mode == h.mode && q.r.n > 0 && q.r.n <= cfg.coalesce_max_n) pos.push_back(k);
+    }
+    return pos;
 }
 
 // Pick a free slot for a request of `ws` bytes: prefer the smallest pool that
@@ -134,43 +157,63 @@ int psdproj_server::pick_slot(size_t ws) {
     return t - slots[cand].held + ws <= cfg.hbm_budget_bytes ? cand : -1;
 }
 
-void psdproj_server::launch(int si, uint64_t ticket, std::unique_lock<std::mutex> &lk) {
+void psdproj_server::launch(int si, const std::vector<uint64_t> &group, std::unique_lock<std::mutex> &lk) {
     Slot &sl = slots[si];
-    Req &q = reqs[ticket];
     sl.busy = true;
-    sl.ticket = ticket;
-    q.slot = si;
-    q.start_ns = now_ns();
+    sl.group = group;
+    const int64_t t0 = now_ns();
+    const int g = (int)group.size();
+    std::vector<int64_t> ns(g), lds(g);
+    std::vector<const float *> xs(g);
+    std::vector<float *> outs(g);
+    for (int k = 0; k < g; ++k) {
+        Req &q = reqs[group[k]];
+        q.slot = si;
+        q.start_ns = t0;
+        ns[k] = q.r.n;
+        lds[k] = q.r.ld;
+        xs[k] = q.r.X;
+        outs[k] = q.r.out;
+    }
+    const int mode = reqs[group[0]].mode;
+    size_t ws = 0;
+    for (uint64_t tk : group) ws += reqs[tk].ws;
     if (cfg.fake_executor) {
-        const psdproj_opts o = psd::default_opts(q.mode);
-        const double n = (double)q.r.n;
-        const double flops = (double)psd::gemm_count_for(o) * n * n * (n + 1.0);
-        sl.fake_end = q.start_ns + 30000 + (int64_t)(flops / (cfg.fake_tflops * 1e12) * 1e9);
-        sl.held = std::max(sl.held, q.ws);
+        const psdproj_opts o = psd::default_opts(mode);
+        double flops = 0.0;
+        for (int k = 0; k < g; ++k) {
+            const double n = (double)ns[k];
+            flops += (double)psd::gemm_count_for(o) * n * n * (n + 1.0);
+        }
+        sl.fake_end = t0 + 30000 + (int64_t)(flops / (cfg.fake_tflops * 1e12) * 1e9);
+        sl.held = std::max(sl.held, ws);
     } else {
-        const psdproj_request r = q.r;
-        const int mode = q.mode;
         hipStream_t st = sl.stream;
         hipEvent_t ev = sl.done;
+        psdproj_info *info = sl.info_dev;
+        psdproj_info *host = sl.info_host;
         lk.unlock();  // enqueueing ~160 launches takes a while; let clients submit
         const psdproj_opts o = psd::default_opts(mode);
-        psdproj_info *info = slots[si].info_dev;
-        int32_t *flag = slots[si].nonfinite_host;
-        *flag = 0;
-        int status = psd::run_projection(o, r.n, r.ld, r.X, r.out, st, info, false);
+        memset(host, 0, sizeof(psdproj_info) * (size_t)g);
+        int status = g == 1 ? psd::run_projection(o, ns[0], lds[0], xs[0], outs[0], st, info, false)
+                            : psd::run_batched(o, g, ns.data(), lds.data(), xs.data(), outs.data(), st, info);
         if (status == PSDPROJ_OK &&
-            (hipMemcpyAsync(flag, &info->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            (hipMemcpyAsync(host, info, sizeof(psdproj_info) * (size_t)g, hipMemcpyDeviceToHost, st) != hipSuccess ||
              hipEventRecord(ev, st) != hipSuccess))
             status = PSDPROJ_ERR_HIP;
         const size_t held = psd::pool_held(st);
         lk.lock();
-        Req &q2 = reqs[ticket];
         slots[si].held = held;
-        if (status != PSDPROJ_OK) {  // nothing left in flight for this request
-            q2.status = status;
-            q2.end_ns = now_ns();
-            q2.finished = true;
+        if (status != PSDPROJ_OK) {  // nothing left in flight for these requests
+            const int64_t t1 = now_ns();
+            for (uint64_t tk : group) {
+                Req &q2 = reqs[tk];
+                q2.status = status;
+                q2.end_ns = t1;
+                q2.finished = true;
+            }
             slots[si].busy = false;
+            slots[si].group.clear();
             cv_done.notify_all();
         }
     }
@@ -189,18 +232,23 @@ void psdproj_server::poll_completions() {
             const hipError_t e = hipEventQuery(sl.done);
             if (e == hipErrorNotReady) continue;
             if (e != hipSuccess) status = PSDPROJ_ERR_HIP;
-            else if (*sl.nonfinite_host) status = PSDPROJ_ERR_NONFINITE;  // out holds NaN
         }
-        Req &q = reqs[sl.ticket];
-        q.end_ns = now_ns();
-        q.status = status;
-        q.finished = true;
+        const int64_t t1 = now_ns();
+        for (size_t k = 0; k < sl.group.size(); ++k) {
+            Req &q = reqs[sl.group[k]];
+            q.end_ns = t1;
+            // a non-finite input leaves NaN in its out (its own entry only)
+            q.status = (status == PSDPROJ_OK && !cfg.fake_executor && sl.info_host[k].nonfinite)
+                           ? PSDPROJ_ERR_NONFINITE : status;
+            q.finished = true;
+            if (q.status == PSDPROJ_OK) {
+                ++n_done;
+                lat_ms.push_back((q.end_ns - q.submit_ns) * 1e-6);
+                last_end = std::max(last_end, q.end_ns);
+            }
+        }
         sl.busy = false;
-        if (status == PSDPROJ_OK) {
-            ++n_done;
-            lat_ms.push_back((q.end_ns - q.submit_ns) * 1e-6);
-            last_end = std::max(last_end, q.end_ns);
-        }
+        sl.group.clear();
         cv_done.notify_all();
     }
 }
@@ -214,15 +262,30 @@ void psdproj_server::loop() {
         // requests at most max_bypass times. launch() drops the lock while it
         // enqueues, so the queue is rescanned after every admission.
         bool admitted = true;
-        while (admitted && !pending.empty()) {
+        while (admitted && !pending.empty() && running() < (int)slots.size()) {
             admitted = false;
             for (size_t idx = 0; idx < pending.size(); ++idx) {
                 const uint64_t tk = pending[idx];
-                const int si = pick_slot(reqs[tk].ws);
+                // the request with the queued ones it can run with, shrunk
+                // from the back until the group's workspace finds a slot
+                // (a group's workspace is taken as the sum of its requests'
+                // single workspaces, which bounds the batched layout's: that
+                // shares one set of tables and drops per-section padding)
+                std::vector<size_t> pos = coalesce(idx);
+                int si = -1;
+                while (!pos.empty()) {
+                    size_t ws = 0;
+                    for (size_t p : pos) ws += reqs[pending[p]].ws;
+                    si = pick_slot(ws);
+                    if (si >= 0 || pos.size() == 1) break;
+                    pos.resize(pos.size() > 2 ? pos.size() / 2 : 1);
+                }
                 if (si >= 0) {
-                    pending.erase(pending.begin() + (long)idx);
-                    if (idx > 0) ++reqs[pending.front()].bypassed;
-                    launch(si, tk, lk);
+                    std::vector<uint64_t> group;
+                    for (size_t p : pos) group.push_back(pending[p]);
+                    for (size_t k = pos.size(); k-- > 0;) pending.erase(pending.begin() + (long)pos[k]);
+                    if (idx > 0 && !pending.empty()) ++reqs[pending.front()].bypassed;
+                    launch(si, group, lk);
                     admitted = true;
                     break;
                 }
@@ -251,19 +314,21 @@ int psdproj_serve_create(const psdproj_serve_config *cfg, psdproj_server **out) 
     if (s->cfg.slots > 64) { delete s; return PSDPROJ_ERR_INVALID_ARG; }
     if (s->cfg.max_bypass <= 0) s->cfg.max_bypass = 8;
     if (s->cfg.fake_tflops <= 0.0) s->cfg.fake_tflops = 500.0;
+    if (s->cfg.coalesce_max_n == 0) s->cfg.coalesce_max_n = 1024;
     s->slots.resize(s->cfg.slots);
     if (!s->cfg.fake_executor) {
         if (hipGetDevice(&s->device) != hipSuccess) { delete s; return PSDPROJ_ERR_HIP; }
         for (Slot &sl : s->slots) {
             if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-                hipMalloc((void **)&sl.info_dev, sizeof(psdproj_info)) != hipSuccess ||
-                hipHostMalloc((void **)&sl.nonfinite_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+                hipMalloc((void **)&sl.info_dev, sizeof(psdproj_info) * kMaxGroup) != hipSuccess ||
+                hipHostMalloc((void **)&sl.info_host, sizeof(psdproj_info) * kMaxGroup, hipHostMallocDefault) !=
+                    hipSuccess) {
                 for (Slot &x : s->slots) {
                     if (x.done) (void)hipEventDestroy(x.done);
                     if (x.stream) (void)hipStreamDestroy(x.stream);
                     if (x.info_dev) (void)hipFree(x.info_dev);
-                    if (x.nonfinite_host) (void)hipHostFree(x.nonfinite_host);
+                    if (x.info_host) (void)hipHostFree(x.info_host);
                 }
                 delete s;
                 return PSDPROJ_ERR_HIP;
@@ -414,7 +479,7 @@ int psdproj_serve_destroy(psdproj_server *s) {
             (void)hipEventDestroy(sl.done);
             (void)hipStreamDestroy(sl.stream);
             (void)hipFree(sl.info_dev);
-            (void)hipHostFree(sl.nonfinite_host);
+            (void)hipHostFree(sl.info_host);
         }
     }
     delete s;

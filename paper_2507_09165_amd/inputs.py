@@ -12,6 +12,7 @@ signs):
 * ``constructed``        X = Q diag(lam) Q^T, Q from the QR of a Gaussian matrix.
 * ``goe``                X = (G + G^T) / sqrt(2 n), G Gaussian (semicircle on [-2, 2]).
 * ``clustered``          20% of the eigenvalues in [-1e-3, 1e-3], 80% in [-1, 1].
+* ``dominant``           a few dominant eigenvalues over a dense [-1, 1] spectrum.
 * ``lowrank_noise``      W W^T / n + sqrt(1e-2) (H + H^T) / sqrt(2 n), rank 500.
 * ``batch_sizes``        256 block sizes, log-uniform in [32, 1024].
 * ``serving_trace``      Poisson arrivals, log-uniform sizes, ADMM-like drift.
@@ -45,6 +46,18 @@ def constructed(n: int, seed_q: int, seed_lam: int, lo: float = -1.0, hi: float 
 def from_spectrum(Q: np.ndarray, lam: np.ndarray) -> np.ndarray:
     X = (Q * lam) @ Q.T
     return (0.5 * (X + X.T)).astype(np.float32)
+
+
+def dominant(n: int, seed: int, top=(1000.0,)):
+    """A few dominant eigenvalues over a dense spectrum (the shape of the
+    paper's hard case: one extremal eigenvalue and many small ones): X = Q
+    diag(lam) Q^T with lam_i = top[i] for the first len(top) and uniform in
+    [-1, 1] otherwise. Returns (X64, Q, lam); X64 is FP64 and symmetric."""
+    Q = haar_orthogonal(n, seed)
+    lam = _rng(seed + 1).uniform(-1.0, 1.0, n)
+    lam[: len(top)] = top
+    X = (Q * lam) @ Q.T
+    return 0.5 * (X + X.T), Q, lam
 
 
 def goe(n: int, seed: int, dtype=np.float32) -> np.ndarray:

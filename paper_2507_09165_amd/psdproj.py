@@ -20,7 +20,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsdproj.so")
 
-MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4, "fp8_fp16_split": 5}
+MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4, "fp8_fp16_split": 5,
+         "ns_fp16": 6, "ns_fp32": 7}
 DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
@@ -37,14 +38,16 @@ class PsdprojError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("split_mask", ctypes.c_uint32), ("split_final", ctypes.c_int),
-                ("lambda_override", ctypes.c_double), ("force_bound_fallback", ctypes.c_int)]
+                ("lambda_override", ctypes.c_double), ("force_bound_fallback", ctypes.c_int),
+                ("deflate", ctypes.c_int)]
 
 
 INFO_DTYPE = np.dtype([("lambda", "<f8"), ("lanczos_lambda", "<f8"), ("sigma", "<f8"),
                        ("residual", "<f8"), ("fro_norm", "<f8"), ("colmax_norm", "<f8"),
                        ("lanczos_steps", "<i4"), ("nonfinite", "<i4"), ("fallback", "<i4"),
-                       ("stages", "<i4")])
-assert INFO_DTYPE.itemsize == 64
+                       ("stages", "<i4"), ("deflated", "<i4"), ("reserved", "<i4")])
+INFO_BYTES = INFO_DTYPE.itemsize
+assert INFO_BYTES == 72
 
 _lib = None
 
@@ -128,12 +131,12 @@ EXPLICIT_MASK = 0x80000000
 
 
 def make_opts(mode="fp16", lanczos_steps=0, split_mask=None, split_final=-1, lambda_override=0.0,
-              force_bound_fallback=False) -> Opts:
+              force_bound_fallback=False, deflate=0) -> Opts:
     """split_mask None selects the mode's default split stages; an integer
     (0 included) is taken as given (the library's explicit-mask bit)."""
     mask = 0 if split_mask is None else (int(split_mask) | EXPLICIT_MASK)
     return Opts(_mode(mode), int(lanczos_steps), mask, int(split_final),
-                float(lambda_override), int(bool(force_bound_fallback)))
+                float(lambda_override), int(bool(force_bound_fallback)), int(deflate))
 
 
 def project(X, out=None, mode="fp16", stream=None):
@@ -158,7 +161,7 @@ def project_ex(X, out=None, stream=None, info=True, **opts):
     if out is None:
         out = torch.empty_like(X)
     o = make_opts(**opts)
-    info_t = torch.zeros(64, dtype=torch.uint8, device=X.device) if info else None
+    info_t = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=X.device) if info else None
     _check(lib().psdproj_project_ex(ctypes.byref(o), n, ld, _ptr(X), _ptr(out), _stream(stream),
                                     _ptr(info_t)), "psdproj_project_ex")
     return out, info_t
@@ -167,7 +170,7 @@ def project_ex(X, out=None, stream=None, info=True, **opts):
 def project_noalloc(X, out, info_t=None, stream=None, **opts):
     """psdproj_project_noalloc: the projection with its workspace in the
     library's fixed device array (no device allocation by the library). out
-    (and info_t, 64 bytes of device memory, if given) are the caller's."""
+    (and info_t, INFO_BYTES bytes of device memory, if given) are the caller's."""
     n, ld = _check_matrix(X)
     if _check_matrix(out, "out") != (n, ld):
         raise ValueError("out must match X in shape and stride")
@@ -189,7 +192,7 @@ def read_info(info_t) -> dict:
 def spectral_bound(X, lanczos_steps=20, stream=None) -> dict:
     import torch
     n, ld = _check_matrix(X)
-    info_t = torch.zeros(64, dtype=torch.uint8, device=X.device)
+    info_t = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=X.device)
     _check(lib().psdproj_spectral_bound(n, ld, _ptr(X), int(lanczos_steps), _stream(stream),
                                         _ptr(info_t)), "psdproj_spectral_bound")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
@@ -222,7 +225,7 @@ def project_batched(Xs, outs=None, mode="bf16", stream=None):
 
 def project_batched_ex(Xs, outs=None, stream=None, info=True, **opts):
     """Batched projection with options; returns (outs, info_tensor) with one
-    64-byte info record per matrix (``read_infos``)."""
+    INFO_BYTES-byte info record per matrix (``read_infos``)."""
     import torch
     if outs is None:
         outs = [torch.empty_like(X) for X in Xs]
@@ -230,7 +233,7 @@ def project_batched_ex(Xs, outs=None, stream=None, info=True, **opts):
     o = make_opts(**opts)
     info_t = None
     if info and cnt:
-        info_t = torch.zeros(64 * cnt, dtype=torch.uint8, device=Xs[0].device)
+        info_t = torch.zeros(INFO_BYTES * cnt, dtype=torch.uint8, device=Xs[0].device)
     _check(lib().psdproj_project_batched_ex(ctypes.byref(o), cnt, ns, lds, xp, op, _stream(stream),
                                             _ptr(info_t)), "psdproj_project_batched_ex")
     return outs, info_t
@@ -322,7 +325,7 @@ def gemm_timing_stop():
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int),
                 ("max_bypass", ctypes.c_int), ("fake_executor", ctypes.c_int),
-                ("fake_tflops", ctypes.c_double)]
+                ("fake_tflops", ctypes.c_double), ("coalesce_max_n", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -366,12 +369,13 @@ def _res_dict(r: Result) -> dict:
 class Server:
     """Continuous-batching projection server (psdproj_serve_*)."""
 
-    def __init__(self, hbm_budget_bytes=0, slots=0, max_bypass=0, fake_executor=False, fake_tflops=0.0):
+    def __init__(self, hbm_budget_bytes=0, slots=0, max_bypass=0, fake_executor=False, fake_tflops=0.0,
+                 coalesce_max_n=0):
         L = lib()
         _serve_sigs(L)
         self._L = L
         cfg = ServeConfig(int(hbm_budget_bytes), int(slots), int(max_bypass), int(bool(fake_executor)),
-                          float(fake_tflops))
+                          float(fake_tflops), int(coalesce_max_n))
         h = ctypes.c_void_p()
         _check(L.psdproj_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "psdproj_serve_create")
         self._h = h

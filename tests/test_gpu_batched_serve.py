@@ -74,7 +74,7 @@ def test_served_results_equal_alone():
     sizes = [64, 300, 1000, 2100, 129, 777, 64, 1500]
     targets = [1e-3, 1e-5, 1e-3, 1e-3, 1e-5, 1e-3, 1e-3, 1e-5]
     Xs = [to_dev(inputs.goe(n, 500 + i)) for i, n in enumerate(sizes)]
-    modes = ["fp32" if t <= 1e-4 else "fp8_fp16_split" for t in targets]
+    modes = ["fp32_emu" if t <= 1e-4 else "fp8_fp16_split" for t in targets]
     alone = [P.project(X, mode=m) for X, m in zip(Xs, modes)]
     torch.cuda.synchronize()
     outs = [torch.full_like(X, float("nan")) for X in Xs]
@@ -110,3 +110,34 @@ def test_served_nonfinite_request_reports_status():
     assert r1["status"] == 10 and r2["status"] == 0
     assert torch.isnan(obad).all()
     assert torch.equal(ook, ref)
+
+
+def test_served_coalesced_group_equals_alone():
+    """Small requests queued behind a long one run as one batched projection
+    (same start, one slot); each result is bitwise the request's result
+    alone, and a non-finite member is reported for itself only."""
+    import torch
+    sizes = [64, 90, 128, 200, 257, 311, 400, 512, 640, 1000, 77, 1024]
+    Xs = [to_dev(inputs.goe(n, 600 + i)) for i, n in enumerate(sizes)]
+    Xb = inputs.goe(150, 41)
+    Xb[3, 7] = Xb[7, 3] = np.inf
+    Xs.append(to_dev(Xb))
+    alone = [P.project(X, mode="fp8_fp16_split") for X in Xs[:-1]]
+    big = to_dev(inputs.goe(4000, 7))
+    obig = torch.empty_like(big)
+    torch.cuda.synchronize()
+    outs = [torch.full_like(X, -1.0) for X in Xs]
+    say("serve coalesced", sizes)
+    with P.Server(slots=1) as s:
+        tb = s.submit(X=big, out=obig, target=1e-3)
+        tks = [s.submit(X=X, out=o, target=1e-3, tag=i) for i, (X, o) in enumerate(zip(Xs, outs))]
+        rb = s.wait(tb, timeout_s=120)
+        rs = [s.wait(t, timeout_s=120) for t in tks]
+    assert rb["status"] == 0
+    assert [r["status"] for r in rs] == [0] * len(sizes) + [10]
+    starts = {r["start_ns"] for r in rs}
+    say(f"  {len(rs)} requests in {len(starts)} launch(es)")
+    assert len(starts) < len(rs)
+    for i in range(len(sizes)):
+        assert torch.equal(outs[i], alone[i]), sizes[i]
+    assert torch.isnan(outs[-1]).all()

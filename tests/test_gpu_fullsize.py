@@ -139,3 +139,36 @@ def test_n4096_fp16_bf16(case):
         say(f"  {mode}: vs oracle {e:.3e}")
         assert torch.equal(out, out.t())
         assert e <= TOL_POLY[mode]
+
+
+@pytest.mark.timeout(600)
+def test_fp32_emu_at_served_sizes():
+    """The serving loop routes 1e-5 targets to FP32_EMU (every product on FP16
+    hi + lo pairs): held to the single-precision tolerance, 1e-5, against the
+    FP64 polynomial on the spectrum at n = 8192, the largest served order (an
+    FP64 eigendecomposition of the same matrix, as above), and against the
+    oracle's matrix-product Algorithm 2 itself at n = 2048."""
+    import torch
+    n = 8192
+    say("fp32_emu n8192")
+    X32 = inputs.goe(n, 17)
+    X = to_dev(X32)
+    del X32
+    w, Q = rocsolver_eigh64(X)
+    out, info_t = P.project_ex(X, mode="fp32_emu")
+    torch.cuda.synchronize()
+    lam = P.read_info(info_t)["lambda"]
+    g = torch.from_numpy(lam * oracle.g_scalar(w.cpu().numpy() / lam, "fp32_emu")).to(w.device)
+    e_poly = _torch_rel(out.double(), (Q.t() * g) @ Q)
+    e_ex = _torch_rel(out.double(), (Q.t() * torch.clamp(w, min=0.0)) @ Q)
+    say(f"  n=8192 fp32_emu: vs poly {e_poly:.3e} vs exact {e_ex:.3e}")
+    assert torch.equal(out, out.t())
+    assert e_poly <= 1e-5
+    del out, X, Q
+    X32 = inputs.goe(2048, 18)
+    out, info_t = P.project_ex(to_dev(X32), mode="fp32_emu")
+    torch.cuda.synchronize()
+    ref, _ = oracle.project_poly(X32.astype(np.float64), "fp32_emu", lam=P.read_info(info_t)["lambda"])
+    e = rel_fro(out.cpu().numpy(), ref)
+    say(f"  n=2048 fp32_emu vs oracle {e:.3e}")
+    assert e <= 1e-5

@@ -33,7 +33,8 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, nm), nm
 
 
-@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu", "fp8_fp16_split"])
+@pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu", "fp8_fp16_split",
+                                  "ns_fp16", "ns_fp32"])
 def test_library_coefficients_match_oracle(mode):
     lib_rows = P.coefficients(mode)
     ora_rows = oracle.stage_rows(mode)
@@ -46,6 +47,8 @@ def test_gemm_counts():
     assert P.gemm_count("bf16") == 46
     assert P.gemm_count("bf16", split_mask=0) == 22  # explicit: no split stage
     assert P.gemm_count("fp32") == 31 == oracle.gemm_count("fp32")
+    assert P.gemm_count("ns_fp16") == 21 == oracle.gemm_count("ns_fp16")  # Section 4.1's count
+    assert P.gemm_count("ns_fp32") == 31 == oracle.gemm_count("ns_fp32")
     assert P.gemm_count("fp32_emu") == 93  # 10 stages x 3 split products x 3 + 3
     # split products cost 2-3 GEMMs each: no split stages, split final only
     assert P.gemm_count("fp16_split", split_mask=0, split_final=1) == 24  # X0 and X_T as pairs

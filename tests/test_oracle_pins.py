@@ -419,11 +419,7 @@ def test_ns_less_accurate_than_composite_on_dense_spectrum():
 # Deflation of dominant eigenpairs (Section 4.1 "Results"; Section 5)
 # --------------------------------------------------------------------------
 def _dominant(n, seed, top):
-    Q = inputs.haar_orthogonal(n, seed)
-    lam = np.random.default_rng(seed + 1).uniform(-1.0, 1.0, n)
-    lam[: len(top)] = top
-    X = (Q * lam) @ Q.T
-    return 0.5 * (X + X.T), Q, lam
+    return inputs.dominant(n, seed, top)
 
 
 def test_deflation_finds_the_dominant_pairs_with_sign():

@@ -25,7 +25,7 @@ def test_all_requests_complete_and_stats():
 
 
 def test_slots_bound_concurrency_and_overlap():
-    with P.Server(slots=3, fake_executor=True, fake_tflops=2.0) as s:  # ~10-20 ms each
+    with P.Server(slots=3, fake_executor=True, fake_tflops=2.0, coalesce_max_n=-1) as s:  # ~10-20 ms each
         tks = [s.submit(n=1000, target=1e-3) for _ in range(9)]
         res = [s.wait(t, timeout_s=60) for t in tks]
     events = sorted([(r["start_ns"], 1) for r in res] + [(r["end_ns"], -1) for r in res])
@@ -129,5 +129,52 @@ def test_mode_from_target():
     with P.Server(slots=2, fake_executor=True) as s:
         a = s.submit(n=100, target=1e-5)
         b = s.submit(n=100, target=1e-3)
-        assert s.wait(a, 10)["mode"] == 0      # FP32
+        assert s.wait(a, 10)["mode"] == 4      # FP32_EMU (FP32-level operands on FP16 pairs)
         assert s.wait(b, 10)["mode"] == 5      # FP8_FP16_SPLIT
+
+
+def test_small_queued_requests_coalesce_into_one_launch():
+    """Requests queued behind a long one, of order <= coalesce_max_n and one
+    mode, start together on one slot (one batched projection); a request of
+    another mode or a larger order is not taken into the group."""
+    with P.Server(slots=1, fake_executor=True, fake_tflops=5.0) as s:
+        big = s.submit(n=3000, target=1e-3)
+        time.sleep(0.05)                      # the big request is running
+        small = [s.submit(n=100 + 7 * i, target=1e-3, tag=i) for i in range(10)]
+        other = s.submit(n=150, target=1e-5)  # another mode
+        large = s.submit(n=1500, target=1e-3)  # above coalesce_max_n
+        rb = s.wait(big, timeout_s=60)
+        rs = [s.wait(t, timeout_s=60) for t in small]
+        ro, rl = s.wait(other, timeout_s=60), s.wait(large, timeout_s=60)
+    assert all(r["status"] == 0 for r in rs + [rb, ro, rl])
+    assert len({r["start_ns"] for r in rs}) == 1 and rs[0]["start_ns"] >= rb["end_ns"]
+    assert len({r["end_ns"] for r in rs}) == 1
+    assert ro["start_ns"] != rs[0]["start_ns"] and rl["start_ns"] != rs[0]["start_ns"]
+
+
+def test_coalescing_off_and_group_cap():
+    with P.Server(slots=1, fake_executor=True, fake_tflops=5.0, coalesce_max_n=-1) as s:
+        big = s.submit(n=3000, target=1e-3)
+        time.sleep(0.05)
+        rs = [s.wait(t, timeout_s=60) for t in [s.submit(n=100, target=1e-3) for _ in range(5)]]
+        s.wait(big, timeout_s=60)
+    assert len({r["start_ns"] for r in rs}) == 5
+    with P.Server(slots=1, fake_executor=True, fake_tflops=5.0) as s:
+        big = s.submit(n=3000, target=1e-3)
+        time.sleep(0.05)
+        rs = [s.wait(t, timeout_s=60) for t in [s.submit(n=64, target=1e-3) for _ in range(40)]]
+        s.wait(big, timeout_s=60)
+    starts = sorted({r["start_ns"] for r in rs})
+    assert len(starts) == 2   # 32 per group at most: 32 + 8
+
+
+def test_group_shrinks_to_fit_the_budget():
+    ws1 = P.workspace_bytes(1000, "fp8_fp16_split")
+    with P.Server(slots=1, fake_executor=True, fake_tflops=5.0, hbm_budget_bytes=int(2.5 * ws1)) as s:
+        big = s.submit(n=1000, target=1e-3)
+        time.sleep(0.02)
+        rs = [s.wait(t, timeout_s=60) for t in [s.submit(n=1000, target=1e-3) for _ in range(8)]]
+        s.wait(big, timeout_s=60)
+        assert s.stats()["peak_bytes_held"] <= int(2.5 * ws1)
+    assert all(r["status"] == 0 for r in rs)
+    assert len({r["start_ns"] for r in rs}) >= 4   # groups of at most two

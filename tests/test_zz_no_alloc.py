@@ -18,7 +18,7 @@ def _pair(X32, mode):
     X = to_dev(X32)
     ref, info_ref = P.project_ex(X, mode=mode)
     out = torch.full_like(X, 7.0)
-    info = torch.zeros(64, dtype=torch.uint8, device=X.device)
+    info = torch.zeros(P.INFO_BYTES, dtype=torch.uint8, device=X.device)
     P.project_noalloc(X, out, info, mode=mode)
     torch.cuda.synchronize()
     return ref, out, P.read_info(info_ref), P.read_info(info)
