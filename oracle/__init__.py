@@ -27,4 +27,4 @@ from .psd import (  # noqa: F401
     start_vector,
     sym_from_upper,
 )
-from . import tables  # noqa: F401
+from . import admm, tables  # noqa: F401

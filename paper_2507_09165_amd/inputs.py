@@ -15,7 +15,7 @@ signs):
 * ``dominant``           a few dominant eigenvalues over a dense [-1, 1] spectrum.
 * ``lowrank_noise``      W W^T / n + sqrt(1e-2) (H + H^T) / sqrt(2 n), rank 500.
 * ``batch_sizes``        256 block sizes, log-uniform in [32, 1024].
-* ``serving_trace``      Poisson arrivals, log-uniform sizes, ADMM-like drift.
+* ``maxcut_graph``       random graphs for the Max-Cut SDPs of the ADMM client.
 """
 from __future__ import annotations
 
@@ -93,23 +93,32 @@ def batch_blocks(sizes, seed: int = 7):
     return [goe(int(n), seed * 100003 + i) for i, n in enumerate(sizes)]
 
 
-def serving_trace(num: int, rate_per_s: float, seed: int = 11, lo: int = 64, hi: int = 8192,
-                  p_fp16: float = 0.7, clients: int = 8):
-    """Poisson arrival times, log-uniform sizes per client stream, accuracy target
-    1e-3 (probability p_fp16) or 1e-5. Returns a list of dicts."""
+def maxcut_graph(n: int, seed: int, avg_degree: float = 5.0):
+    """Edges (i, j), i < j, of an Erdos-Renyi graph with the given mean degree
+    and unit weights: the shape of the Max-Cut SDP instances of Section 4.2
+    (G55: n = 5000, 12498 edges). Returns an (m, 2) int array."""
     rng = _rng(seed)
-    gaps = rng.exponential(1.0 / rate_per_s, size=num)
-    t = np.cumsum(gaps)
-    client_n = np.clip(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=clients))), lo, hi).astype(int)
-    reqs = []
-    for i in range(num):
-        c = int(rng.integers(clients))
-        reqs.append({"t": float(t[i]), "client": c, "n": int(client_n[c]),
-                     "target": 1e-3 if rng.uniform() < p_fp16 else 1e-5})
-    return reqs
+    m = int(round(avg_degree * n / 2))
+    seen = set()
+    edges = []
+    while len(edges) < m:
+        i, j = (int(v) for v in rng.integers(0, n, size=2))
+        if i == j:
+            continue
+        a, b = (i, j) if i < j else (j, i)
+        if (a, b) in seen:
+            continue
+        seen.add((a, b))
+        edges.append((a, b))
+    return np.array(edges, dtype=np.int64)
 
 
-def admm_like_iterate(Y_prev: np.ndarray, seed: int, var: float = 1e-3) -> np.ndarray:
-    """Y_k = Y_{k-1} + symmetric Gaussian perturbation with entry variance var/n."""
-    n = Y_prev.shape[0]
-    return (Y_prev.astype(np.float64) + np.sqrt(var) * goe(n, seed, np.float64)).astype(np.float32)
+def laplacian(n: int, edges) -> np.ndarray:
+    """Graph Laplacian L = D - W (unit weights), FP64."""
+    L = np.zeros((n, n))
+    for a, b in edges:
+        L[a, b] -= 1.0
+        L[b, a] -= 1.0
+        L[a, a] += 1.0
+        L[b, b] += 1.0
+    return L
