@@ -240,6 +240,27 @@ const char *psdproj_status_string(int status);
  * change. Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
 int psdproj_tune(const char *key, int64_t value);
 
+/* ---- autotuner ----------------------------------------------------------
+ * psdproj_autotune: for each order in sizes[count] (1 <= n <= 65535) times
+ * whole projections in `mode` of a random symmetric matrix of that order
+ * (device-generated; the tuner allocates and frees it) under every candidate
+ * tile policy of the order's size class (quarter octaves of n): 128 tiles
+ * only, and for n >= 1024 outside FP32 also 256-tile rounds whose last
+ * partial round runs as up to 1, 2, 4 or 8 K-chunks per tile. The fastest
+ * becomes the class's policy for later plans of this process (in every mode
+ * with the same work precision) and, when cache_path is not NULL, is written
+ * to that text file (lines of other devices, modes and classes are kept).
+ * Synchronises `stream`. The policies change results only through the
+ * rounding of K-split tiles (single and batched calls of an order still agree
+ * bitwise). psdproj_tune_load applies the lines of a cache file that match
+ * the current device (GPU architecture and CU count) and returns how many, or
+ * minus a status; the first plan of a process also applies the file named by
+ * the environment variable PSDPROJ_TUNE_CACHE. psdproj_tune("class_choices_clear",
+ * 0) drops all per-class policies. */
+int psdproj_autotune(int mode, const int64_t *sizes, int count, const char *cache_path,
+                     psdproj_stream_t stream);
+int psdproj_tune_load(const char *path);
+
 /* ---- serving: a continuous-batching request loop -------------------------
  * A server owns `slots` HIP streams (default priority) and a scheduler thread.
  * Requests are admitted in arrival order as soon as a slot is free and the
@@ -311,6 +332,31 @@ int psdproj_serve_cancel(psdproj_server *s, uint64_t ticket);
 int psdproj_serve_stats(psdproj_server *s, psdproj_serve_statistics *st);
 /* Drain running work, cancel queued requests, free streams and workspaces. */
 int psdproj_serve_destroy(psdproj_server *s);
+
+/* ---- ADMM for SDP: the elementwise steps --------------------------------
+ * The three-step ADMM of Section 4.2 (its ADMM equation) for SDPs whose
+ * constraint map is the diagonal, A X = diag(X), so that A A^T = I and
+ * A^T y = Diag(y) (the Max-Cut family):
+ *     y = b / sigma - diag(X / sigma + S - C),   W = C - Diag(y) - X / sigma,
+ *     S = Pi(W)  (any psdproj_project* call),    X = X + sigma (S + Diag(y) - C).
+ * X, S, C, W: device FP32 n x n, column-major, leading dimension ld, both
+ * triangles (caller-owned; the projection reads W's upper triangle and writes
+ * both triangles of S). b, y: device FP64 vectors of n. Queued on `stream`;
+ * the return value reports argument and launch errors only.
+ * psdproj_admm_dual writes y and W (n <= 65535).
+ * psdproj_admm_primal updates X in place and writes to res (device, at least
+ * PSDPROJ_ADMM_RES_DOUBLES doubles; entries 8.. are its scratch):
+ *     res[0] = ||diag(X) - b||_2, res[1] = ||Diag(y) + S - C||_F,
+ *     res[2] = <C, X>, res[3] = b^T y, res[4] = ||b||_2, res[5] = ||C||_F,
+ * from which the paper's surrogate residual (its three-term stopping test
+ * before the precision switch) follows. Sums are FP64 in a fixed order. */
+#define PSDPROJ_ADMM_GROUPS 512
+#define PSDPROJ_ADMM_RES_DOUBLES (8 + 4 * PSDPROJ_ADMM_GROUPS)
+int psdproj_admm_dual(int64_t n, int64_t ld, const float *X, const float *S, const float *C,
+                      const double *b, double sigma, double *y, float *W, psdproj_stream_t stream);
+int psdproj_admm_primal(int64_t n, int64_t ld, float *X, const float *S, const float *C,
+                        const double *y, const double *b, double sigma, double *res,
+                        psdproj_stream_t stream);
 
 /* ---- product timing (tooling) ---------------------------------------------
  * psdproj_gemm_timing_start clears earlier records and brackets the launches

@@ -61,10 +61,50 @@ int gemm_pick_tile(int64_t K, int dtype) {
 static std::atomic<int64_t> g_big_min{kBigMinDefault};
 static std::atomic<int> g_tail_cus{0};  // 0: the device's CU count
 
+// Per-size-class choices of the autotuner, keyed by (dtype, class).
+static std::mutex g_class_mu;
+static std::map<std::pair<int, int>, std::pair<int, int>> g_class_choice;  // -> (tile, ksplit)
+
+int gemm_size_class(int64_t n) {
+    int c = 0;
+    double x = (double)(n > 1 ? n : 1);
+    while (x >= 2.0) { x *= 0.5; c += 4; }
+    // x in [1, 2): quarter octaves 2^(q/4)
+    const double q1 = 1.189207115002721, q2 = 1.414213562373095, q3 = 1.681792830507429;
+    return c + (x >= q3 ? 3 : x >= q2 ? 2 : x >= q1 ? 1 : 0);
+}
+
+void gemm_set_class_choice(int dtype, int cls, int tile, int ksplit) {
+    {
+        std::lock_guard<std::mutex> lk(g_class_mu);
+        g_class_choice[{dtype, cls}] = {tile, ksplit};
+    }
+    ++g_tile_gen;
+}
+
+void gemm_clear_class_choices() {
+    {
+        std::lock_guard<std::mutex> lk(g_class_mu);
+        g_class_choice.clear();
+    }
+    ++g_tile_gen;
+}
+
+bool gemm_class_choice(int dtype, int64_t n, int *tile, int *ksplit) {
+    std::lock_guard<std::mutex> lk(g_class_mu);
+    auto it = g_class_choice.find({dtype, gemm_size_class(n)});
+    if (it == g_class_choice.end()) return false;
+    *tile = it->second.first;
+    *ksplit = it->second.second;
+    return true;
+}
+
 bool gemm_use_big(int64_t n, int dtype) {
     const int o = g_tile_override;
     if (o == 128) return false;
     if (o == 256) return true;
+    int tile = 0, ks = 0;
+    if (dtype != DT_F32 && gemm_class_choice(dtype, n, &tile, &ks)) return tile == 256;
     return dtype != DT_F32 && n >= g_big_min;
 }
 int gemm_tail_cus(int device_cus) {
@@ -110,7 +150,14 @@ int gemm_tile_generation() { return g_tile_gen; }
 // not depend on the other matrices of a batch.
 static std::atomic<int> g_ksplit_max{8};  // tuning hook: most K-chunks per tile (1: never split)
 
-void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out) {
+int gemm_ksplit_for(int64_t n, int dtype) {
+    int tile = 0, ks = 0;
+    if (gemm_class_choice(dtype, n, &tile, &ks)) return ks;
+    return g_ksplit_max;
+}
+
+void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, const std::vector<int> &ksplit,
+                     int cus, TileLists &out) {
     out.big.clear();
     out.small_plain.clear();
     out.small_all.clear();
@@ -127,7 +174,7 @@ void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &bi
         std::vector<WorkItem> t;
         append_tile_order(t, (uint32_t)m, (int)(np[m] / kTile2));
         const size_t tail = (g_tile_override == kTile2 || cus <= 0) ? 0 : t.size() % (size_t)cus;
-        const int chunks = tail ? std::min<int>((int)((size_t)cus / tail), g_ksplit_max) : 0;
+        const int chunks = tail ? std::min<int>((int)((size_t)cus / tail), ksplit[m]) : 0;
         out.big.insert(out.big.end(), t.begin(), t.end() - tail);
         for (size_t k = t.size() - tail; k < t.size(); ++k) {
             const WorkItem w = t[k];

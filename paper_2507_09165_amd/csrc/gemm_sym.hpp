@@ -69,7 +69,20 @@ struct TileLists {
     std::vector<uint4> split, fixup;
     int64_t parts = 0;
 };
-void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, int cus, TileLists &out);
+// ksplit: most K-chunks per tail tile of each matrix (gemm_ksplit_for).
+void gemm_tile_lists(const std::vector<int64_t> &np, const std::vector<bool> &big, const std::vector<int> &ksplit,
+                     int cus, TileLists &out);
+// Per-size-class tile choice (the autotuner's): for orders of class
+// gemm_size_class(n) in work precision dtype, tile 128 (128 tiles only) or
+// 256 (256-tile rounds, tails as up to `ksplit` K-chunks). Without a choice
+// the fixed rules above apply. Setting or clearing a choice bumps the tuning
+// generation (plans are rebuilt).
+int gemm_size_class(int64_t n);  // quarter octaves: floor(4 log2 n)
+void gemm_set_class_choice(int dtype, int cls, int tile, int ksplit);
+void gemm_clear_class_choices();
+bool gemm_class_choice(int dtype, int64_t n, int *tile, int *ksplit);
+// Most K-chunks per tail tile for an n x n matrix in dtype.
+int gemm_ksplit_for(int64_t n, int dtype);
 // Incremented whenever a tuning hook changes the tile choice.
 int gemm_tile_generation();
 // CU count the tail rule uses (the device's unless the tuning hook set one).

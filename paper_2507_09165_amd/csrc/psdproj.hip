@@ -267,6 +267,7 @@ void layout_plan(Plan &P) {
     P.n_vec = P.n_symv = P.n_cast = 0;
     std::vector<int64_t> nps;
     std::vector<bool> big;
+    std::vector<int> ksplit;
     for (int64_t n : P.ns) {
         P.mats.push_back(mat_layout(n, P.sp, P.steps, P.deflate > 0 ? P.defl_ld : 0));
         const MatLayout &L = P.mats.back();
@@ -275,8 +276,9 @@ void layout_plan(Plan &P) {
         P.n_cast += cast_tile_count(L.np);
         nps.push_back(L.np);
         big.push_back(plan_big(n, P.sp));
+        ksplit.push_back(gemm_ksplit_for(n, P.sp.dtype));
     }
-    gemm_tile_lists(nps, big, P.cus, P.tiles);
+    gemm_tile_lists(nps, big, ksplit, P.cus, P.tiles);
     P.n_gemm[0] = (int64_t)P.tiles.big.size();
     P.n_gemm[1] = (int64_t)P.tiles.small_plain.size();
     P.n_gemm[2] = (int64_t)P.tiles.small_all.size();
@@ -654,6 +656,7 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
 
 int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, int64_t defl_ld, hipStream_t s,
             Plan **out) {
+    load_env_tune_cache();
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     StagePlan sp;
@@ -797,6 +800,12 @@ psdproj_opts default_opts(int mode) {
     o.mode = mode;
     o.split_final = -1;
     return o;
+}
+
+int mode_dtype(int mode) {
+    psdproj_opts o = default_opts(mode);
+    StagePlan sp;
+    return make_stage_plan(o, sp) ? sp.dtype : -1;
 }
 
 size_t workspace_bytes_batch(const int64_t *ns, int count, int mode) {
@@ -1001,6 +1010,10 @@ int psdproj_tune(const char *key, int64_t value) {
         g_ld_pad = value;
         for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
         for (auto &kv : g_scratch) kv.second.plan.reset();
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "class_choices_clear")) {  // drop the autotuner's per-size-class choices
+        gemm_clear_class_choices();
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "gemm_big_min")) {  // products of n >= value use the 256 tile (0: default)

@@ -15,6 +15,10 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
 int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_t *ld, const float *const *X,
                 float *const *out, hipStream_t s, psdproj_info *info);
 psdproj_opts default_opts(int mode);
+// Work precision (DType) of a mode's products, or -1 for a bad mode.
+int mode_dtype(int mode);
+// Apply the tuning cache named by PSDPROJ_TUNE_CACHE (once per process).
+void load_env_tune_cache();
 // Workspace bytes of one batched call over the orders ns in mode.
 size_t workspace_bytes_batch(const int64_t *ns, int count, int mode);
 // Workspace bytes a projection of size n in mode needs (0 for a bad mode).

@@ -272,6 +272,10 @@ void psdproj_server::loop() {
                 // single workspaces, which bounds the batched layout's: that
                 // shares one set of tables and drops per-section padding)
                 std::vector<size_t> pos = coalesce(idx);
+                if (idx > 0) {  // every member passes the head: at most its remaining bypasses
+                    const int left = cfg.max_bypass - reqs[pending.front()].bypassed;
+                    if ((int)pos.size() > left) pos.resize(left > 1 ? left : 1);
+                }
                 int si = -1;
                 while (!pos.empty()) {
                     size_t ws = 0;
@@ -284,7 +288,7 @@ void psdproj_server::loop() {
                     std::vector<uint64_t> group;
                     for (size_t p : pos) group.push_back(pending[p]);
                     for (size_t k = pos.size(); k-- > 0;) pending.erase(pending.begin() + (long)pos[k]);
-                    if (idx > 0 && !pending.empty()) ++reqs[pending.front()].bypassed;
+                    if (idx > 0 && !pending.empty()) reqs[pending.front()].bypassed += (int)group.size();
                     launch(si, group, lk);
                     admitted = true;
                     break;

@@ -83,6 +83,10 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     L.psdproj_sym_gemm_pair8.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float, vp, vp, c_int, c_int, c_int, c_int, vp]
+    L.psdproj_autotune.argtypes = [c_int, ctypes.POINTER(i64), c_int, ctypes.c_char_p, vp]
+    L.psdproj_tune_load.argtypes = [ctypes.c_char_p]
+    L.psdproj_admm_dual.argtypes = [i64, i64, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]
+    L.psdproj_admm_primal.argtypes = [i64, i64, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.psdproj_gemm_timing_start.argtypes = []
     L.psdproj_gemm_timing_stop.argtypes = [ctypes.c_void_p, c_int]
     for name in ("psdproj_gemm_timing_start", "psdproj_gemm_timing_stop",
@@ -90,7 +94,8 @@ def lib() -> ctypes.CDLL:
                  "psdproj_spectral_bound",
                  "psdproj_project_batched", "psdproj_project_batched_ex", "psdproj_gemm_count",
                  "psdproj_coefficients",
-                 "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8"):
+                 "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8",
+                 "psdproj_admm_dual", "psdproj_admm_primal", "psdproj_autotune", "psdproj_tune_load"):
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -264,6 +269,22 @@ def coefficients(mode="fp16") -> np.ndarray:
 
 def tune(key: str, value: int):
     _check(lib().psdproj_tune(key.encode(), int(value)), f"psdproj_tune({key})")
+
+
+def autotune(mode, sizes, cache_path=None, stream=None):
+    """Time the tile policies of each order's size class and keep the fastest
+    (psdproj_autotune); writes cache_path when given."""
+    arr = (ctypes.c_int64 * len(sizes))(*[int(n) for n in sizes])
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().psdproj_autotune(_mode(mode), arr, len(sizes), path, _stream(stream)), "psdproj_autotune")
+
+
+def tune_load(path) -> int:
+    """Apply a tuning cache file; returns the number of lines applied."""
+    r = int(lib().psdproj_tune_load(str(path).encode()))
+    if r < 0:
+        raise PsdprojError(-r, "psdproj_tune_load")
+    return r
 
 
 def release():
