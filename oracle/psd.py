@@ -252,10 +252,31 @@ def final_combine(X0: np.ndarray, Y: np.ndarray, lam: float) -> np.ndarray:
     return 0.5 * (P + P.T)
 
 
+# Adaptive depth (Section 5, "Limitations and future work": the depth
+# adjusted online from spectral estimates). Our reading: the change of the
+# iterate in a stage, ||X_{t+1} - X_t||_F / ||X_t||_F, measures how far the
+# spectrum still is from the fixed points +-1 of a sign iteration; stages of a
+# sign iteration without rescale stop as soon as it is at most `adaptive_tol`.
+# Those stages are every Newton-Schulz step, and `adaptive_extra` quintic
+# Newton-Schulz steps (15 x - 10 x^3 + 3 x^5) / 8 appended to the composite
+# filter (the paper's single table ends with two such stages). The designed
+# composite stages themselves always run: their rescale keeps the iterate off
+# +-1 until the last one.
+NS_QUINTIC = (15.0 / 8.0, -10.0 / 8.0, 3.0 / 8.0)
+
+
+def relative_change(Y_new: np.ndarray, Y: np.ndarray) -> float:
+    ny = float(np.linalg.norm(Y))
+    return float(np.linalg.norm(Y_new - Y)) / ny if ny > 0.0 else 0.0
+
+
 def project_poly(X, mode: str = "fp16", lam: float | None = None,
-                 steps: int = LANCZOS_STEPS, force_fallback: bool = False):
+                 steps: int = LANCZOS_STEPS, force_fallback: bool = False,
+                 adaptive_tol: float = 0.0, adaptive_extra: int = 0):
     """Algorithm 2 in FP64. ``lam`` overrides the spectral bound (so that the
     oracle evaluates exactly the function the device evaluated).
+    ``adaptive_tol`` > 0 stops the adaptive stages (see above) at the first
+    relative change <= the tolerance; ``info["stages"]`` counts the stages run.
 
     Returns (P, info) with P FP64 n x n symmetric."""
     Xs = sym_from_upper(X)
@@ -273,12 +294,27 @@ def project_poly(X, mode: str = "fp16", lam: float | None = None,
         return np.zeros_like(Xs), info
     X0 = Xs / lam
     Y = X0
+    stages = 0
     if mode in NS_ITERS:
         for _ in range(NS_ITERS[mode]):
-            Y = newton_schulz_stage(Y)
+            Y_new = newton_schulz_stage(Y)
+            d = relative_change(Y_new, Y)
+            Y = Y_new
+            stages += 1
+            if adaptive_tol > 0.0 and d <= adaptive_tol:
+                break
     else:
         for a, b, c in stage_rows(mode):
             Y = filter_stage(Y, a, b, c)
+            stages += 1
+        for _ in range(int(adaptive_extra)):
+            Y_new = filter_stage(Y, *NS_QUINTIC)
+            d = relative_change(Y_new, Y)
+            Y = Y_new
+            stages += 1
+            if adaptive_tol > 0.0 and d <= adaptive_tol:
+                break
+    info["stages"] = stages
     return final_combine(X0, Y, lam), info
 
 

@@ -465,3 +465,72 @@ def test_deflation_fixes_one_dominant_eigenvalue():
         P, _ = oracle.project_deflated(X, "fp16", kmax=k)
         e.append(np.linalg.norm(P - ex) / np.linalg.norm(rest))
     assert e[0] > 1e-2 and e[1] < 1e-4
+
+
+# --------------------------------------------------------------------------
+# Adaptive depth (Section 5, "Limitations and future work")
+# --------------------------------------------------------------------------
+def _quintic_by_error(x):
+    """(15 x - 10 x^3 + 3 x^5) / 8 through its fixed-point form:
+    1 - f(x) = (1 - x)^3 (3 x^2 + 9 x + 8) / 8 for x >= 0, odd in x."""
+    a = np.abs(x)
+    return np.sign(x) * (1.0 - (1.0 - a) ** 3 * (3.0 * a * a + 9.0 * a + 8.0) / 8.0)
+
+
+def test_adaptive_ns_stops_where_the_scalar_iteration_converges():
+    """On X = Q diag(l) Q^T the relative change of a Newton-Schulz step is
+    ||s_k(l) - s_{k-1}(l)|| / ||s_{k-1}(l)|| with s the scalar iteration (its
+    error recursion); the adaptive run stops at the first step whose change is
+    at most the tolerance, and equals the fixed run of that many steps."""
+    X32, Q, lam = inputs.constructed(300, 0, 1, lo=0.2, hi=1.0)
+    X = (Q * lam) @ Q.T
+    X = 0.5 * (X + X.T)
+    lt = oracle.spectral_bound(X)["lam"]
+    x = lam / lt
+    changes = []
+    for k in range(1, 16):
+        xn = _ns_by_error_recursion(x, 1)
+        changes.append(np.linalg.norm(xn - x) / np.linalg.norm(x))
+        x = xn
+    for tol in (2e-3, 1e-5, 1e-8):
+        k = next(i + 1 for i, c in enumerate(changes) if c <= tol)
+        assert changes[k - 1] < 0.5 * tol and changes[k - 2] > 2.0 * tol  # clear-cut
+        P, info = oracle.project_poly(X, "ns_fp32", lam=lt, adaptive_tol=tol)
+        assert info["stages"] == k
+        ref = oracle.project_spectral(
+            Q, lam, lambda l: lt * 0.5 * (l / lt) * (1.0 + _ns_by_error_recursion(l / lt, k)))
+        np.testing.assert_allclose(P, ref, atol=1e-12)
+
+
+def test_adaptive_extra_quintic_stages_spectral_identity():
+    """Composite filter plus extra quintic stages: the matrix result is the
+    scalar composite followed by the quintic's fixed-point form, per
+    eigenvalue; with tol = 0 every extra stage runs."""
+    n = 60
+    Q = inputs.haar_orthogonal(n, 9)
+    lam = np.random.default_rng(10).uniform(-1.0, 1.0, n)
+    X = (Q * lam) @ Q.T
+    X = 0.5 * (X + X.T)
+    lt = 1.05
+    P, info = oracle.project_poly(X, "fp16", lam=lt, adaptive_extra=2)
+    assert info["stages"] == 9
+
+    def g(l):
+        y = oracle.psd.composite_scalar(l / lt, oracle.stage_rows("fp16"))
+        y = _quintic_by_error(_quintic_by_error(y))
+        return lt * 0.5 * (l / lt) * (1.0 + y)
+    np.testing.assert_allclose(P, oracle.project_spectral(Q, lam, g), atol=1e-12)
+
+
+def test_adaptive_extra_stages_reach_the_exact_projection():
+    """On a GOE spectrum one or two quintic stages after the composite filter
+    take the exact-arithmetic error from ~3e-5 to rounding level, and the
+    tolerance stops them there."""
+    X = inputs.goe(300, 1).astype(np.float64)
+    ex = oracle.project_exact_eigh(X)
+    P0, i0 = oracle.project_poly(X, "fp16")
+    P1, i1 = oracle.project_poly(X, "fp16", adaptive_tol=1e-8, adaptive_extra=6)
+    e0 = np.linalg.norm(P0 - ex) / np.linalg.norm(ex)
+    e1 = np.linalg.norm(P1 - ex) / np.linalg.norm(ex)
+    assert e0 > 1e-5 and e1 < 1e-12
+    assert i0["stages"] == 7 and 8 <= i1["stages"] <= 10
