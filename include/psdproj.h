@@ -110,6 +110,19 @@ typedef struct {
                                  Single projections only (batched calls return
                                  PSDPROJ_ERR_UNSUPPORTED); the workspace gains an
                                  ld x n FP32 copy. */
+    double adaptive_tol;      /* adaptive depth (Section 5): > 0 ends the sign
+                                 iteration at the first stage whose relative
+                                 change ||X_{t+1} - X_t||_F / ||X_t||_F is at
+                                 most this (FP64 sums over the stored iterates);
+                                 later stages then skip their products. Applies
+                                 to every Newton-Schulz step, and to the
+                                 adaptive_extra stages. Modes without split
+                                 products only (else PSDPROJ_ERR_UNSUPPORTED);
+                                 psdproj_info.stages reports the stages run. */
+    int adaptive_extra;       /* composite modes: 0..(16 - T) quintic
+                                 Newton-Schulz stages (15x - 10x^3 + 3x^5)/8
+                                 appended to the table's T stages (with
+                                 adaptive_tol = 0 all of them run) */
 } psdproj_opts;
 
 /* Written on the device by psdproj_project_ex / psdproj_spectral_bound. */

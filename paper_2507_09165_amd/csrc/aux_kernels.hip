@@ -766,6 +766,88 @@ hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, int e8, hipStrea
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive depth: the relative change ||X_new - X_old||_F / ||X_old||_F of a
+// stage, over the 64 x 64 tile pairs of the cast work list (off-diagonal
+// tiles count twice, diagonal tiles their upper half twice and the diagonal
+// once), per-tile sums in a fixed order, then per matrix in list order.
+template <typename T>
+__global__ __launch_bounds__(256) void stage_delta_kernel(const MatDesc *D, const WorkItem *W, int sn, int so,
+                                                          double *part) {
+    const WorkItem wi = W[blockIdx.x];
+    const MatDesc &dm = D[wi.x];
+    double dd = 0.0, nn = 0.0;
+    if (!dm.scal->done) {
+        int bi, bj;
+        tile_of((int)wi.y, bi, bj);
+        const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64, n = dm.n, ld = dm.ldw;
+        const T *Xn = (const T *)dm.hi[sn];
+        const T *Xo = (const T *)dm.hi[so];
+        const int64_t i = i0 + (threadIdx.x & 63);
+        for (int c = threadIdx.x >> 6; c < 64; c += 4) {
+            const int64_t j = j0 + c;
+            if (i >= n || j >= n || (bi == bj && i > j)) continue;
+            const double w = (bi == bj && i == j) ? 1.0 : 2.0;
+            const double a = (double)(float)Xn[j * ld + i], b = (double)(float)Xo[j * ld + i];
+            dd += w * (a - b) * (a - b);
+            nn += w * b * b;
+        }
+    }
+    __shared__ double sh[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dd += __shfl_xor(dd, off, 64);
+        nn += __shfl_xor(nn, off, 64);
+    }
+    if (lane == 0) {
+        sh[wave] = dd;
+        sh[4 + wave] = nn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * (size_t)blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        part[2 * (size_t)blockIdx.x + 1] = ((sh[4] + sh[5]) + sh[6]) + sh[7];
+    }
+}
+
+// One thread per matrix: unless converged earlier, the latest iterate is in
+// slot sn after `stage` stages; may_stop: converged once the change <= tol.
+__global__ void stage_final_kernel(const MatDesc *D, const double *part, int sn, int stage, int may_stop, double tol) {
+    if (threadIdx.x != 0) return;
+    const MatDesc &dm = D[blockIdx.x];
+    Scalars *sc = dm.scal;
+    if (sc->done) return;
+    sc->cur_slot = sn;
+    sc->stages_run = stage;
+    if (!may_stop) return;
+    double dd = 0.0, nn = 0.0;
+    for (int k = 0; k < dm.cast_count; ++k) {
+        dd += part[2 * (size_t)(dm.cast_first + k)];
+        nn += part[2 * (size_t)(dm.cast_first + k) + 1];
+    }
+    const double d = nn > 0.0 ? sqrt(dd / nn) : 0.0;
+    sc->delta = d;
+    if (d <= tol) sc->done = 1;
+}
+
+hipError_t stage_check(const BatchLaunch &B, int dtype, int sn, int so, int stage, bool may_stop, double tol,
+                       double *part, hipStream_t s) {
+    if (B.count == 0) return hipSuccess;
+    if (may_stop && B.n_cast) {
+        const dim3 g((unsigned)B.n_cast), blk(256);
+        switch (dtype) {
+            case 0: hipLaunchKernelGGL(stage_delta_kernel<float>, g, blk, 0, s, B.desc, B.w_cast, sn, so, part); break;
+            case 1: hipLaunchKernelGGL(stage_delta_kernel<f16>, g, blk, 0, s, B.desc, B.w_cast, sn, so, part); break;
+            case 2: hipLaunchKernelGGL(stage_delta_kernel<bf16>, g, blk, 0, s, B.desc, B.w_cast, sn, so, part); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    hipLaunchKernelGGL(stage_final_kernel, dim3((unsigned)B.count), dim3(64), 0, s, B.desc, part, sn, stage,
+                       may_stop ? 1 : 0, tol);
+    return hipGetLastError();
+}
+
 size_t lanczos_work_doubles(int64_t n, int steps) {
     const int64_t nbv = (n + kRows - 1) / kRows;
     const int64_t tiles = symv_tile_count(n);

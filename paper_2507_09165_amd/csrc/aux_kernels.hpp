@@ -40,6 +40,14 @@ hipError_t deflate_remove(const DeflLaunch &L, hipStream_t s);
 // out += sum max(mu, 0) z z^T (both triangles).
 hipError_t deflate_addback(const DeflLaunch &L, hipStream_t s);
 
+// Adaptive depth after a stage whose iterate is in slot sn (the previous one
+// in so): per matrix not yet converged, record sn and the stage count and,
+// when may_stop, its relative change (FP64 sums over the cast work list into
+// part, 2 doubles per item), converged once <= tol. dtype: 0 FP32, 1 FP16,
+// 2 BF16.
+hipError_t stage_check(const BatchLaunch &B, int dtype, int sn, int so, int stage, bool may_stop, double tol,
+                       double *part, hipStream_t s);
+
 size_t lanczos_work_doubles(int64_t n, int steps);
 int64_t symv_tile_count(int64_t n);
 int64_t vec_block_count(int64_t n);

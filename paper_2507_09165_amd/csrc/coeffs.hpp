@@ -43,6 +43,9 @@ constexpr StageCoef kTildeHalf[7] = {
 // precision (21 and 31 products with the final one), without stage rescale.
 constexpr StageCoef kNewtonSchulz = {1.5, -0.5, 0.0};
 constexpr int kNewtonSchulzHalf = 10;
+// Quintic Newton-Schulz step (15 x - 10 x^3 + 3 x^5) / 8 (the last two stages
+// of Table 1's Stage-I column): the extra stages of adaptive depth.
+constexpr StageCoef kNewtonSchulzQuintic = {15.0 / 8.0, -10.0 / 8.0, 3.0 / 8.0};
 constexpr int kNewtonSchulzSingle = 15;
 
 // Number of stages followed by the 1/1.001 (single) or 1/1.01 (half) rescale.

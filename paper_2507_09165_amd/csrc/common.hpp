@@ -31,6 +31,13 @@ struct Scalars {
     int32_t stop;       // breakdown flag
     int32_t nonfinite;  // input had Inf/NaN
     int32_t fallback;   // guard replaced the Lanczos bound
+    // adaptive depth: converged (later adaptive stages are skipped), the work
+    // slot holding the latest iterate, stages run, last relative change
+    int32_t done;
+    int32_t cur_slot;
+    int32_t stages_run;
+    int32_t pad_;
+    double delta;
     double alpha[32];
     double beta[32];
     double s[32];       // Ritz vector in the Krylov basis
@@ -74,6 +81,8 @@ struct MatDesc {
     int32_t pad_;
     double *U;            // deflation only: X v_j of every Lanczos step (n x steps), else null
     DeflState *defl;      // deflation only, else null
+    int32_t cast_first;   // this matrix's run in the cast work list (adaptive-depth sums)
+    int32_t cast_count;
 };
 
 // Caller-owned input and output of one matrix: X upper triangle and out,

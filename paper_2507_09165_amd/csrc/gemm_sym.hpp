@@ -34,6 +34,10 @@ struct GemmArgs {
     // and their FP32 partial tiles (kTile2 x kTile2 floats each)
     const uint4 *split;
     float *part;
+    // adaptive depth: 1 = a stage product, skipped once the matrix's iterate
+    // has converged; 2 = the final product, whose right operand is the slot
+    // of the latest iterate (Scalars::cur_slot) instead of sr
+    int adaptive;
 };
 
 // ls / rs: L / R carry lo halves. bm: tile edge (128 or 256; it must divide

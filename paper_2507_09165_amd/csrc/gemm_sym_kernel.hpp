@@ -202,6 +202,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         part = e.w;
     }
     const MatDesc &dm = g.D[tv.x];
+    if (g.adaptive == 1 && dm.scal->done) return;  // converged: later stages are skipped (uniform per workgroup)
+    const int sr = g.adaptive == 2 ? dm.scal->cur_slot : g.sr;
     const int bi = (int)(tv.y & 0xFFFFu), bj = (int)(tv.y >> 16);
     const int64_t i0 = (int64_t)bi * BM;
     const int64_t j0 = (int64_t)bj * BM;
@@ -219,8 +221,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         int p = 0;
         src[p++] = (const uint8_t *)dm.hi[g.sl];
         if constexpr (LS) src[p++] = (const uint8_t *)dm.lo[g.sl];
-        src[p++] = (const uint8_t *)dm.hi[g.sr];
-        if constexpr (RS) src[p++] = (const uint8_t *)dm.lo[g.sr];
+        src[p++] = (const uint8_t *)dm.hi[sr];
+        if constexpr (RS) src[p++] = (const uint8_t *)dm.lo[sr];
     }
     // Direct global->LDS loads: one wave instruction moves 64 x 16 bytes into
     // 1 KB of contiguous LDS (lane l -> byte 16 l). The K-tile of all panels

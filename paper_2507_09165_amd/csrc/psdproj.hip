@@ -56,6 +56,10 @@ constexpr uint32_t kExplicitMask = 0x80000000u;
 struct StagePlan {
     int T = 0;
     bool cubic = false;  // Newton-Schulz steps a X + b X^3 (two products each)
+    // adaptive depth: stages t >= adapt_from are skipped once the iterate's
+    // relative change in a stage is at most opts.adaptive_tol
+    bool adaptive = false;
+    int adapt_from = 0;
     double a[16], b[16], c[16];
     int dtype = DT_F32;
     uint32_t split_mask = 0;
@@ -126,6 +130,9 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
                 p.b[t] = kNewtonSchulz.b;
                 p.c[t] = kNewtonSchulz.c;
             }
+            if (o.adaptive_extra != 0 || !(o.adaptive_tol >= 0.0)) return false;
+            p.adaptive = o.adaptive_tol > 0.0;  // every step may end the iteration
+            p.adapt_from = 0;
             pair_exponents(p);
             return true;
         default: return false;
@@ -137,6 +144,16 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
         p.b[t] = tab[t].b * s;
         p.c[t] = tab[t].c * s;
     }
+    // adaptive depth: extra quintic Newton-Schulz stages after the table
+    if (o.adaptive_extra < 0 || T + o.adaptive_extra > 16 || !(o.adaptive_tol >= 0.0)) return false;
+    for (int k = 0; k < o.adaptive_extra; ++k) {
+        p.a[T + k] = kNewtonSchulzQuintic.a;
+        p.b[T + k] = kNewtonSchulzQuintic.b;
+        p.c[T + k] = kNewtonSchulzQuintic.c;
+    }
+    p.T = T + o.adaptive_extra;
+    p.adaptive = o.adaptive_tol > 0.0 && o.adaptive_extra > 0;
+    p.adapt_from = T;
     if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT || o.mode == PSDPROJ_MODE_BF16) {
         const uint32_t def = o.mode == PSDPROJ_MODE_BF16 ? kDefaultSplitMaskBf16 : kDefaultSplitMask;
         const uint32_t m = (o.split_mask & kExplicitMask) ? (o.split_mask & ~kExplicitMask)
@@ -209,6 +226,8 @@ struct Plan {
     // key
     int mode = -1, steps = 0, split_final = 0;
     int deflate = 0;       // pairs to deflate (single projections only)
+    int stages = 0;        // filter stages (with adaptive-depth extras)
+    bool adaptive = false;
     int64_t defl_ld = 0;   // caller's leading dimension when deflating
     uint32_t split_mask = 0;
     std::vector<int64_t> ns;
@@ -219,7 +238,7 @@ struct Plan {
     // matrix (split products without the 256 tile); K-chunks and fixups of
     // the split tail tiles, and their partial tiles
     size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[3] = {0, 0, 0}, total = 0;
-    size_t off_split = 0, off_fixup = 0, off_part = 0;
+    size_t off_split = 0, off_fixup = 0, off_part = 0, off_adapt = 0;
     int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[3] = {0, 0, 0}, n_split = 0, n_fixup = 0;
     int gemm_bm[3] = {256, 128, 128};
     TileLists tiles;
@@ -256,7 +275,8 @@ struct Plan {
     bool same_key(const psdproj_opts &o, const StagePlan &rq, int st, const std::vector<int64_t> &n,
                   int64_t dld) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
-               ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld;
+               ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld &&
+               stages == rq.T && adaptive == rq.adaptive;
     }
 };
 
@@ -295,6 +315,7 @@ void layout_plan(Plan &P) {
     P.off_split = take(sizeof(uint4) * (size_t)P.n_split);
     P.off_fixup = take(sizeof(uint4) * (size_t)P.n_fixup);
     P.off_part = take(kPartBytes * (size_t)P.tiles.parts);
+    P.off_adapt = take(P.sp.adaptive ? sizeof(double) * 2 * (size_t)P.n_cast : 0);
     for (const MatLayout &L : P.mats) P.mat_off.push_back(take(L.total));
     P.total = off;
 }
@@ -339,6 +360,8 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
         }
         for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
+        d.cast_first = (int32_t)wc.size();
+        d.cast_count = (int32_t)cast_tile_count(L.np);
         for (int64_t i = 0; i < cast_tile_count(L.np); ++i) wc.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
     }
     const std::vector<WorkItem> *wg[3] = {&P.tiles.big, &P.tiles.small_plain, &P.tiles.small_all};
@@ -393,7 +416,7 @@ int get_workspace(Pool &p, hipStream_t s, size_t bytes, void **out) {
 }
 
 // Numerical status of matrix blockIdx.x into the info buffer its I/O names.
-__global__ void info_kernel(const MatDesc *D, const IoArg *io_tab, IoArg io0, int stages) {
+__global__ void info_kernel(const MatDesc *D, const IoArg *io_tab, IoArg io0, int stages, int adaptive) {
     if (threadIdx.x != 0) return;
     psdproj_info *info = (psdproj_info *)io_of(io_tab, io0, blockIdx.x).info;
     if (!info) return;
@@ -407,7 +430,7 @@ __global__ void info_kernel(const MatDesc *D, const IoArg *io_tab, IoArg io0, in
     info->lanczos_steps = s->k;
     info->nonfinite = s->nonfinite;
     info->fallback = s->fallback;
-    info->stages = stages;
+    info->stages = adaptive ? s->stages_run : stages;
     info->deflated = D[blockIdx.x].defl ? D[blockIdx.x].defl->count : 0;
     info->reserved = 0;
 }
@@ -529,7 +552,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (bound_only) {
-        if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, 0);
+        if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, 0, 0);
         return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
     }
     const StagePlan &p = P.sp;
@@ -584,7 +607,17 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
     int cur = 0;
     bool cur_split = (p.split_mask & 1u) != 0;
+    double *adapt_part = (double *)(b + P.off_adapt);
+    const int check_dt = p.dtype == DT_F16X8 ? DT_F16 : p.dtype;  // unsplit FP8-pair storage is FP16
+    // adaptive depth: after stage t (its iterate in slot sn), record the slot
+    // once the designed stages are done, and test the change of every
+    // skippable stage
+    auto check = [&](int t, int sn, int so) -> hipError_t {
+        if (!p.adaptive || t + 1 < p.adapt_from) return hipSuccess;
+        return stage_check(B, check_dt, sn, so, t + 1, t >= p.adapt_from, o.adaptive_tol, adapt_part, s);
+    };
     for (int t = 0; t < p.T; ++t) {
+        g.adaptive = (p.adaptive && t >= p.adapt_from) ? 1 : 0;
         const bool sp = (p.split_mask >> t) & 1u;
         const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         int pa = -1, pb = -1;
@@ -596,7 +629,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
             if (e != hipSuccess) return PSDPROJ_ERR_HIP;
             e = product(cur, false, pa, false, cur, false, (float)p.a[t], (float)p.b[t], 0.f, pb, EPI_STORE,
                         p.ex[t + 1]);
-            if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+            if (e != hipSuccess || check(t, pb, cur) != hipSuccess) return PSDPROJ_ERR_HIP;
             cur = pb;
             continue;
         }
@@ -611,15 +644,18 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         // X' = a X + X B
         e = product(cur, xs, pb, sp, cur, cur_split, (float)p.a[t], 1.f, 0.f, pa,
                     next_split ? EPI_STORE_SPLIT : EPI_STORE, p.ex[t + 1]);
-        if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+        if (e != hipSuccess || check(t, pa, cur) != hipSuccess) return PSDPROJ_ERR_HIP;
         cur = pa;
         cur_split = next_split;
     }
-    // out = (X + lam X0 X_T) / 2
+    // out = (X + lam X0 X_T) / 2 (adaptive depth: X_T is the latest iterate's slot)
+    g.adaptive = p.adaptive ? 2 : 0;
     e = product(0, p.split_final, cur, p.split_final, -1, false, 0.f, 1.f, 0.f, 0, EPI_FINAL, 0);
+    g.adaptive = 0;
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (P.deflate > 0 && deflate_addback(DL, s) != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, p.T);
+    if (want_info)
+        hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, p.T, p.adaptive ? 1 : 0);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
 }
 
@@ -640,6 +676,8 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     P->mode = o.mode;
     P->deflate = o.deflate;
     P->defl_ld = defl_ld;
+    P->stages = sp.T;
+    P->adaptive = sp.adaptive;
     P->steps = steps;
     P->sp = sp;
     P->split_mask = sp.split_mask;
@@ -755,6 +793,7 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     if (!X || (!out && !bound_only)) return PSDPROJ_ERR_INVALID_ARG;
     if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
     if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
+    if (tmp.adaptive && (tmp.split_mask || tmp.split_final)) return PSDPROJ_ERR_UNSUPPORTED;
     psdproj_opts oo = o;
     if (bound_only) oo.deflate = 0;
     const int64_t defl_ld = oo.deflate > 0 ? ld : 0;
@@ -784,6 +823,7 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
     }
     if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
     if (o.deflate > 0) return PSDPROJ_ERR_UNSUPPORTED;  // deflation: single projections only
+    if (tmp.adaptive && (tmp.split_mask || tmp.split_final)) return PSDPROJ_ERR_UNSUPPORTED;
     if (ns.empty()) return PSDPROJ_OK;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
     if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;

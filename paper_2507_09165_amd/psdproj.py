@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("split_mask", ctypes.c_uint32), ("split_final", ctypes.c_int),
                 ("lambda_override", ctypes.c_double), ("force_bound_fallback", ctypes.c_int),
-                ("deflate", ctypes.c_int)]
+                ("deflate", ctypes.c_int), ("adaptive_tol", ctypes.c_double), ("adaptive_extra", ctypes.c_int)]
 
 
 INFO_DTYPE = np.dtype([("lambda", "<f8"), ("lanczos_lambda", "<f8"), ("sigma", "<f8"),
@@ -136,12 +136,13 @@ EXPLICIT_MASK = 0x80000000
 
 
 def make_opts(mode="fp16", lanczos_steps=0, split_mask=None, split_final=-1, lambda_override=0.0,
-              force_bound_fallback=False, deflate=0) -> Opts:
+              force_bound_fallback=False, deflate=0, adaptive_tol=0.0, adaptive_extra=0) -> Opts:
     """split_mask None selects the mode's default split stages; an integer
     (0 included) is taken as given (the library's explicit-mask bit)."""
     mask = 0 if split_mask is None else (int(split_mask) | EXPLICIT_MASK)
     return Opts(_mode(mode), int(lanczos_steps), mask, int(split_final),
-                float(lambda_override), int(bool(force_bound_fallback)), int(deflate))
+                float(lambda_override), int(bool(force_bound_fallback)), int(deflate),
+                float(adaptive_tol), int(adaptive_extra))
 
 
 def project(X, out=None, mode="fp16", stream=None):

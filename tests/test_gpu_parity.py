@@ -388,3 +388,49 @@ def test_deflation_refused_in_batches_and_bounded():
     torch.cuda.synchronize()
     assert P.read_info(info_t)["deflated"] == 0
     assert torch.equal(out, ref)
+
+
+def _gapped(n, seed):
+    X32, Q, lam = inputs.constructed(n, seed, seed + 1, lo=0.2, hi=1.0)
+    return X32
+
+
+@pytest.mark.parametrize("mode,tol,k", [("ns_fp32", 1e-5, 8), ("ns_fp16", 2e-3, 7)])
+def test_adaptive_newton_schulz_stops_early(mode, tol, k):
+    """Adaptive depth on a spectrum in [0.2, 1]: the device ends the iteration
+    at the same step as the oracle (the scalar iteration's changes bracket
+    the tolerance by a wide margin there) and matches its result."""
+    X32 = _gapped(500, 0)
+    out, info = _run(X32, mode, adaptive_tol=tol)
+    ref, oinfo = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"], adaptive_tol=tol)
+    e = rel_fro(out, ref)
+    say(f"adaptive {mode}: stages {info['stages']} (oracle {oinfo['stages']}), vs oracle {e:.3e}")
+    assert info["stages"] == oinfo["stages"] == k
+    assert e <= TOL_POLY[mode]
+
+
+def test_adaptive_extra_stages_and_batches():
+    """Composite FP32 plus up to 3 quintic stages (tol 1e-6): the GOE block
+    stops after 2 extra stages like the oracle; in a batch with a gapped
+    block each matrix keeps its own count, and results equal the single
+    calls bitwise."""
+    import torch
+    Xa = inputs.goe(700, 5)
+    out, info = _run(Xa, "fp32", adaptive_tol=1e-6, adaptive_extra=3)
+    ref, oinfo = oracle.project_poly(Xa.astype(np.float64), "fp32", lam=info["lambda"], adaptive_tol=1e-6,
+                                     adaptive_extra=3)
+    say(f"adaptive fp32+3: stages {info['stages']} (oracle {oinfo['stages']}), vs oracle {rel_fro(out, ref):.3e}")
+    assert info["stages"] == oinfo["stages"]
+    assert rel_fro(out, ref) <= 1e-5
+    Xs = [to_dev(Xa), to_dev(_gapped(300, 3))]
+    outs, infos_t = P.project_batched_ex(Xs, mode="ns_fp32", adaptive_tol=1e-5)
+    singles = [P.project_ex(X, mode="ns_fp32", adaptive_tol=1e-5) for X in Xs]
+    torch.cuda.synchronize()
+    infos = P.read_infos(infos_t)
+    for o, (s_out, s_info), inf in zip(outs, singles, infos):
+        assert torch.equal(o, s_out)
+        assert inf["stages"] == P.read_info(s_info)["stages"]
+    assert infos[0]["stages"] == 15 and infos[1]["stages"] < 15
+    with pytest.raises(P.PsdprojError) as e:
+        P.project_ex(Xs[0], mode="fp16_split", adaptive_tol=1e-3, adaptive_extra=1)
+    assert e.value.status == 2
