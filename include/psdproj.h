@@ -85,14 +85,20 @@ typedef enum {
                                     MFMA, 31 products                                */
 } psdproj_mode;
 
+/* split_mask flag: split only the B product of the masked stages */
+#define PSDPROJ_SPLIT_B_ONLY 0x40000000u
+
 typedef struct {
     int mode;                 /* psdproj_mode */
     int lanczos_steps;        /* 0 -> 20 (Section 3.4); at most 32 */
     uint32_t split_mask;      /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: bit t set ->
                                  stage t+1 uses split products; 0 -> the mode's
                                  default (stages 2-3; BF16: 1-4). Bit 31 set:
-                                 bits 0..30 are taken as given even when all zero
-                                 (e.g. 0x80000000 = no split stage) */
+                                 bits 0..29 are taken as given even when all zero
+                                 (e.g. 0x80000000 = no split stage). Bit 30
+                                 (PSDPROJ_SPLIT_B_ONLY): in the masked stages only
+                                 B = b A + c A^2 is split; A = X X stays plain and
+                                 X' = a X + B X has one split operand */
     int split_final;          /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: -1 default (0),
                                  0 plain, 1 split final product */
     double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */
@@ -216,9 +222,10 @@ size_t psdproj_workspace_bytes(int64_t n, int mode);
 
 /* Number of n_p x n_p products (FP16-product equivalents) a projection runs:
  * 3 per stage + 1 for plain modes (22 half, 31 single); an FP16 split product
- * counts 3 (2 if one operand is split), an FP8_FP16_SPLIT split product 2.
- * opts may be NULL (then `mode` defaults apply). */
-int psdproj_gemm_count(const psdproj_opts *opts, int mode);
+ * counts 3 (2 if one operand is split), an FP8_FP16_SPLIT split product 2
+ * (1.5 if one operand is split). opts may be NULL (then `mode` defaults
+ * apply). Returns -1 for bad options. */
+double psdproj_gemm_count(const psdproj_opts *opts, int mode);
 
 /* Host copy of the run-time coefficients of `mode` (rescale folded in):
  * abc[3 t + 0..2] = (a_t, b_t, c_t). Returns T, or -1 for a bad mode or when
@@ -421,8 +428,11 @@ int psdproj_sym_gemm(int dtype, int64_t n_p, int64_t ld, const void *L, const vo
  * MFMA fragment pair covers. The buffer holds n_p ld bytes. e_l, e_r, e_c0, e_d are the pair exponents of L, R,
  * C0 and D (|e| <= 40). Lx and Rx are both given (pair product: L_hi R_hi on
  * FP16 MFMAs plus both cross terms on FP8 MFMAs, with the codes of M_hi 2^e
- * formed in registers) or both NULL; C0x != NULL adds the pair correction of
- * C0; Dx != NULL writes D's codes. Queued on `stream` like psdproj_sym_gemm. */
+ * formed in registers), Lx alone (one-sided product: L_hi R_hi plus the single
+ * cross term L_lo R_hi, whose FP8 MFMAs take 64 K per instruction), or both
+ * NULL; Rx without Lx is PSDPROJ_ERR_UNSUPPORTED. C0x != NULL adds the pair
+ * correction of C0; Dx != NULL writes D's codes. Queued on `stream` like
+ * psdproj_sym_gemm. */
 int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *Lx,
                            const void *R, const void *Rx, const void *C0, const void *C0x,
                            float alpha, float beta, float gamma, void *D, void *Dx,

@@ -142,7 +142,10 @@ __device__ __forceinline__ void wait_lgkmcnt() {
 // X8: split parts are FP8 pairs (FP16 hi + stored e4m3 lo codes; the hi
 // codes are formed in registers) instead of FP16 hi + FP16 lo; the pair
 // product is L_hi R_hi on FP16 MFMAs plus both cross terms on one FP8 MFMA per
-// 32 K. Requires T = f16 and LS == RS.
+// 32 K. Requires T = f16, and L split whenever R is. With L split and R plain
+// (one-sided) the only cross term is L_lo R_hi: 32 K of it fill half an FP8
+// MFMA, so the codes of two consecutive K-units go into one MFMA (the first
+// unit's held in registers; an odd last unit is padded with zero codes).
 //
 // COMB (both operands split, 128 tile): each operand's LDS row interleaves
 // its two parts, [hi of BK K | lo (or FP8 pair) of the same BK K], so two
@@ -160,8 +163,9 @@ __device__ __forceinline__ void wait_lgkmcnt() {
 // partial round of 256 tiles.
 template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8, int KS>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
-    static_assert(!X8 || (sizeof(T) == 2 && LS == RS), "FP8 pairs: FP16 hi, both operands split");
+    static_assert(!X8 || (sizeof(T) == 2 && (LS || !RS)), "FP8 pairs: FP16 hi, L split whenever R is");
     constexpr bool PAIR8 = X8 && LS;          // FP8 cross terms in the main loop
+    constexpr bool ONE8 = PAIR8 && !RS;       // one-sided: L_lo R_hi only
     constexpr bool COMB = LS && RS && !X8 && BM == 128;
     constexpr int NCH = ROWB / 16;            // 16-byte chunks per LDS row
     constexpr int NLP = LS ? 2 : 1;
@@ -169,9 +173,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int NPAN = COMB ? 2 : NLP + NRP;  // LDS panels per stage
     constexpr int PANEL = BM * ROWB;
     // PAIR8 stage: [L hi: 64-byte rows | L codes: 32-byte rows | R hi | R codes]
-    // for 32 K; the hi codes of the cross terms are formed in registers
+    // for 32 K (ONE8: no R codes); the hi codes of the cross terms are formed
+    // in registers
     constexpr int P8HI = BM * 64, P8LO = BM * 32;
-    constexpr int STAGE = PAIR8 ? 2 * (P8HI + P8LO) : NPAN * PANEL;
+    constexpr int STAGE = PAIR8 ? 2 * P8HI + (RS ? 2 : 1) * P8LO : NPAN * PANEL;
     constexpr int TB = PAIR8 ? 64 : (COMB ? ROWB / 2 : ROWB);  // bytes per K-tile (hi buffer)
     constexpr int BK = TB / (int)sizeof(T);     // K per tile
     constexpr int HCH = COMB ? NCH / 2 : 0;     // COMB: first chunk of the lo part
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const int kb = (wave * NLD + j) * 1024;  // byte offset in the stage
         gstep[j] = TB;
         if constexpr (PAIR8) {
-            // panels: L hi, L codes, R hi, R codes (every 1-KB load lies in one)
+            // panels: L hi, L codes, R hi[, R codes] (every 1-KB load lies in one)
             const int side = kb >= P8HI + P8LO ? 1 : 0;
             const int off = kb - side * (P8HI + P8LO);
             const bool is_hi = off < P8HI;
@@ -337,8 +342,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const int64_t ke = kb + kch < nk_all ? kb + kch : nk_all;
         // Fragments of one K-unit, [part][MFMA block m]. Plain and FP16 pairs:
         // one part per operand panel. FP8 pairs: L_hi (two 16-K substeps),
-        // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo).
-        constexpr int NFP = PAIR8 ? 6 : NLP + NRP;
+        // L codes (hi, lo), R_hi (two substeps), R codes (hi, lo); ONE8 has no
+        // R codes.
+        constexpr int NFP = PAIR8 ? (RS ? 6 : 5) : NLP + NRP;
         typedef u32x4 Frag[NFP][MI];
         // E8M0 scale codes 2^(c - 127), replicated into every byte
         const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma unroll
                 for (int m = 0; m < MI; ++m) {
                     f[2][m] = *(const u32x4 *)(ll + ra_[m] * 32 + ((hg ^ ((ra_[m] >> 3) & 1)) << 4));
-                    f[5][m] = *(const u32x4 *)(rl + rb_[m] * 32 + ((hg ^ ((rb_[m] >> 3) & 1)) << 4));
+                    if constexpr (RS) f[NFP - 1][m] = *(const u32x4 *)(rl + rb_[m] * 32 + ((hg ^ ((rb_[m] >> 3) & 1)) << 4));
                 }
                 return;
             } else if constexpr (COMB) {
@@ -416,10 +422,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
 #pragma unroll
                 for (int ni = 0; ni < MI; ++ni) {
                     if constexpr (PAIR8) {
-                        mma(acc[mi][ni], f[0][mi], f[3][ni], T{});
-                        mma(acc[mi][ni], f[1][mi], f[4][ni], T{});
-                        mma_x8(acc[mi][ni], hi8_codes(f[0][mi], f[1][mi], cva), f[2][mi], f[5][ni],
-                               hi8_codes(f[3][ni], f[4][ni], cvb), sa8, sb8);
+                        static_assert(!PAIR8 || NSUB == 1, "FP8 pairs run their own K-unit below");
                     } else if constexpr (LS || RS) {
                         mma(acc[mi][ni], f[0][mi], scale_frag(f[NLP][ni], T{}), T{});
                         if constexpr (RS) mma(acc[mi][ni], f[0][mi], f[NLP + 1][ni], T{});
@@ -435,6 +438,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         // needed (in-order return)
         constexpr int NDS = NFP * MI < 15 ? NFP * MI : 15;
         Frag fr[2];
+        // ONE8: the first K-unit of a pair's L lo codes and R hi codes
+        u32x4 held_l[ONE8 ? MI : 1], held_r[ONE8 ? MI : 1];
         // LDS ring of NST stages, K-tiles prefetched NST - 1 iterations ahead.
         // Every wave issues exactly NLD loads per iteration (the index is clamped
         // at the end), so "tile kt+1 has landed" is vmcnt <= NLD * (NST - 2).
@@ -473,8 +478,10 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         // 1, codes): start on each group as it lands; every
                         // accumulator still sees substep 0, 1, then the cross terms
                         const Frag &f = fr[sub & 1];
+                        // reads outstanding after substep 0 / substep 1 landed
+                        constexpr int W0 = (RS ? 4 : 3) * MI, W1 = (RS ? 2 : 1) * MI;
                         __builtin_amdgcn_sched_barrier(0);
-                        wait_lgkmcnt<(4 * MI < 15 ? 4 * MI : 15)>();
+                        wait_lgkmcnt<(W0 < 15 ? W0 : 15)>();
 #pragma unroll
                         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -483,7 +490,7 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                                 il(MI * MI < NLD ? MI * MI : NLD);
                             }
                         __builtin_amdgcn_sched_barrier(0);
-                        wait_lgkmcnt<2 * MI>();
+                        wait_lgkmcnt<W1>();
 #pragma unroll
                         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -494,15 +501,32 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         u32x4 ha[MI], hb[MI];
 #pragma unroll
                         for (int m = 0; m < MI; ++m) {
-                            ha[m] = hi8_codes(f[0][m], f[1][m], cva);
+                            if constexpr (RS) ha[m] = hi8_codes(f[0][m], f[1][m], cva);
                             hb[m] = hi8_codes(f[3][m], f[4][m], cvb);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<0>();
+                        if constexpr (RS) {
 #pragma unroll
-                        for (int mi = 0; mi < MI; ++mi)
+                            for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-                            for (int ni = 0; ni < MI; ++ni) mma_x8(acc[mi][ni], ha[mi], f[2][mi], f[5][ni], hb[ni], sa8, sb8);
+                                for (int ni = 0; ni < MI; ++ni)
+                                    mma_x8(acc[mi][ni], ha[mi], f[2][mi], f[NFP - 1][ni], hb[ni], sa8, sb8);
+                        } else if (kr & 1) {
+                            // second unit of a pair: [held | this unit] of L lo codes
+                            // against [held | this unit] of R hi codes
+#pragma unroll
+                            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                                for (int ni = 0; ni < MI; ++ni)
+                                    mma_x8(acc[mi][ni], held_l[mi], f[2][mi], held_r[ni], hb[ni], sa8, sb8);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < MI; ++m) {
+                                held_l[m] = f[2][m];
+                                held_r[m] = hb[m];
+                            }
+                        }
                     } else {
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<0>();
@@ -521,6 +545,16 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                 wait_vmcnt<NLD * (NST - 2)>();
                 __builtin_amdgcn_s_barrier();
                 load_frags(smem + (int)((kr + 1) % NST) * STAGE, 0, fr[0]);
+            }
+            if constexpr (ONE8) {
+                // an odd last unit: its codes against zero codes
+                if ((ke - kb) & 1) {
+                    const u32x4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+                    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < MI; ++ni) mma_x8(acc[mi][ni], held_l[mi], z, held_r[ni], z, sa8, sb8);
+                }
             }
             __builtin_amdgcn_s_waitcnt(0);
         }
@@ -730,11 +764,18 @@ static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s, in
 }
 
 template <int EPI>
-static hipError_t launch_x8(const GemmArgs &g, bool pair, int bm, int64_t ntiles, hipStream_t s, int ks) {
-    if (pair) {
+static hipError_t launch_x8(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s, int ks) {
+    if (ls && rs) {
         switch (bm) {
             case 256: return launch_bm<f16, true, true, EPI, 256, true>(g, ntiles, s, ks);
             case 128: return launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s, ks);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (ls) {
+        switch (bm) {
+            case 256: return launch_bm<f16, true, false, EPI, 256, true>(g, ntiles, s, ks);
+            case 128: return launch_bm<f16, true, false, EPI, 128, true>(g, ntiles, s, ks);
         }
         return hipErrorInvalidValue;
     }
@@ -777,8 +818,8 @@ hipError_t gemm_launch_part(const GemmArgs &g, bool ls, bool rs, int bm, int64_t
     } else if constexpr (DT == DT_BF16) {
         return launch_split<bf16, EPI>(g, ls, rs, bm, ntiles, s, ks);
     } else {
-        if (ls != rs) return hipErrorInvalidValue;
-        return launch_x8<EPI>(g, ls, bm, ntiles, s, ks);
+        if (rs && !ls) return hipErrorInvalidValue;  // one-sided pairs: the split operand on the left
+        return launch_x8<EPI>(g, ls, rs, bm, ntiles, s, ks);
     }
 }
 

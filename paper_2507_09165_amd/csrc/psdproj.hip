@@ -52,6 +52,10 @@ constexpr uint32_t kDefaultSplitMaskBf16 = 0xF;
 // split_mask bit 31: take bits 0..30 as given, even when they are all zero
 // (a zero mask otherwise selects the mode's default).
 constexpr uint32_t kExplicitMask = 0x80000000u;
+// split_mask bit 30: in the masked stages only B = b A + c A^2 is kept as a
+// pair; A = X X stays plain and X' = a X + B X is a one-sided split product
+// (split operand B on the left, since B and X commute).
+constexpr uint32_t kSplitBOnly = PSDPROJ_SPLIT_B_ONLY;
 
 struct StagePlan {
     int T = 0;
@@ -64,6 +68,7 @@ struct StagePlan {
     int dtype = DT_F32;
     uint32_t split_mask = 0;
     bool split_final = false;
+    bool b_only = false;  // kSplitBOnly: only B is split in the masked stages
     // FP8-pair code exponents (DT_F16X8): X_t (t = 0..T), A and B of stage t
     int ex[17], ea[16], eb[16];
 };
@@ -159,6 +164,7 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
         const uint32_t m = (o.split_mask & kExplicitMask) ? (o.split_mask & ~kExplicitMask)
                                                           : (o.split_mask ? o.split_mask : def);
         p.split_mask = m & ((1u << T) - 1);
+        p.b_only = (m & kSplitBOnly) != 0 && p.split_mask != 0;
         p.split_final = o.split_final < 0 ? kDefaultSplitFinal : o.split_final != 0;
     } else if (o.mode == PSDPROJ_MODE_FP32_EMU) {
         // every product on hi + lo FP16 pairs: ~22-bit operands, FP32 accumulation
@@ -230,6 +236,7 @@ struct Plan {
     bool adaptive = false;
     int64_t defl_ld = 0;   // caller's leading dimension when deflating
     uint32_t split_mask = 0;
+    bool b_only = false;
     std::vector<int64_t> ns;
     // layout
     StagePlan sp;
@@ -276,7 +283,7 @@ struct Plan {
                   int64_t dld) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
                ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld &&
-               stages == rq.T && adaptive == rq.adaptive;
+               stages == rq.T && adaptive == rq.adaptive && b_only == rq.b_only;
     }
 };
 
@@ -556,7 +563,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
     }
     const StagePlan &p = P.sp;
-    const bool x0_split = p.split_final || (p.split_mask & 1u);
+    const bool x0_split = p.split_final || ((p.split_mask & 1u) && !p.b_only);
     e = cast_x0(B, p.dtype, x0_split, p.ex[0], s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
 
@@ -606,7 +613,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     };
     // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
     int cur = 0;
-    bool cur_split = (p.split_mask & 1u) != 0;
+    bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
     double *adapt_part = (double *)(b + P.off_adapt);
     const int check_dt = p.dtype == DT_F16X8 ? DT_F16 : p.dtype;  // unsplit FP8-pair storage is FP16
     // adaptive depth: after stage t (its iterate in slot sn), record the slot
@@ -619,7 +626,9 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     for (int t = 0; t < p.T; ++t) {
         g.adaptive = (p.adaptive && t >= p.adapt_from) ? 1 : 0;
         const bool sp = (p.split_mask >> t) & 1u;
-        const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
+        // whether X' is stored split (B-only plans: only for a split final product)
+        const bool next_split = p.b_only ? (t + 1 == p.T && p.split_final)
+                                         : (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         int pa = -1, pb = -1;
         for (int k = 1; k < 4; ++k)
             if (k != cur) { if (pa < 0) pa = k; else if (pb < 0) pb = k; }
@@ -631,6 +640,21 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
                         p.ex[t + 1]);
             if (e != hipSuccess || check(t, pb, cur) != hipSuccess) return PSDPROJ_ERR_HIP;
             cur = pb;
+            continue;
+        }
+        if (p.b_only && sp) {
+            // A = X X; B = b A + c A A, stored as a pair; X' = a X + B X with
+            // only B split (X is never split before the final product here)
+            e = product(cur, false, cur, false, -1, false, 0.f, 1.f, 0.f, pa, EPI_STORE, p.ea[t]);
+            if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+            e = product(pa, false, pa, false, pa, false, (float)p.b[t], (float)p.c[t], 0.f, pb, EPI_STORE_SPLIT,
+                        p.eb[t]);
+            if (e != hipSuccess) return PSDPROJ_ERR_HIP;
+            e = product(pb, true, cur, false, cur, false, (float)p.a[t], 1.f, 0.f, pa,
+                        next_split ? EPI_STORE_SPLIT : EPI_STORE, p.ex[t + 1]);
+            if (e != hipSuccess || check(t, pa, cur) != hipSuccess) return PSDPROJ_ERR_HIP;
+            cur = pa;
+            cur_split = next_split;
             continue;
         }
         const bool xs = sp && cur_split;  // X enters as a pair only in a split stage
@@ -682,6 +706,7 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     P->sp = sp;
     P->split_mask = sp.split_mask;
     P->split_final = sp.split_final;
+    P->b_only = sp.b_only;
     P->ns = ns;
     P->tile_gen = gemm_tile_generation();
     P->split_big = gemm_split_big(sp.dtype);
@@ -885,24 +910,32 @@ void pool_release(hipStream_t s) {
     g_pool.erase(it);
 }
 
-int gemm_count_for(const psdproj_opts &o) {
+double gemm_count_for(const psdproj_opts &o) {
     StagePlan p;
     if (!make_stage_plan(o, p)) return -1;
-    // an FP16 pair product is 3 FP16 products; an FP8 pair product is one FP16
-    // product plus one FP8 product of twice the K at twice the rate
+    // an FP16 pair product is 3 FP16 products (2 with one operand split); an
+    // FP8 pair product is one FP16 product plus one FP8 product of twice the K
+    // at twice the rate (one-sided: of the same K, 1.5 in all)
     if (p.cubic) return 2 * p.T + 1;
-    const int pair = p.dtype == DT_F16X8 ? 2 : 3;
-    int g = 0;
-    bool cur_split = (p.split_mask & 1u) != 0;
+    const double pair = p.dtype == DT_F16X8 ? 2.0 : 3.0;
+    const double one = p.dtype == DT_F16X8 ? 1.5 : 2.0;
+    double g = 0;
+    bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
     for (int t = 0; t < p.T; ++t) {
         const bool sp = (p.split_mask >> t) & 1u;
+        if (p.b_only) {
+            g += sp ? 2.0 + one : 3.0;  // X X and A A plain; B X one-sided in split stages
+            continue;
+        }
         const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         const bool xs = sp && cur_split;
-        g += xs ? pair : 1;             // X X
-        g += sp ? pair : 1;             // A A
-        g += sp ? (xs ? pair : 2) : 1;  // X B
+        g += xs ? pair : 1;               // X X
+        g += sp ? pair : 1;               // A A
+        g += sp ? (xs ? pair : one) : 1;  // X B
         cur_split = next_split;
     }
+    // a split final product multiplies X0 and X_T both split (B-only plans:
+    // X0 split, X_T split by the last stage)
     g += p.split_final ? pair : 1;
     return g;
 }
@@ -965,7 +998,7 @@ int psdproj_project_batched_ex(const psdproj_opts *opts, int count, const int64_
 
 size_t psdproj_workspace_bytes(int64_t n, int mode) { return workspace_bytes_for(n, mode); }
 
-int psdproj_gemm_count(const psdproj_opts *opts, int mode) {
+double psdproj_gemm_count(const psdproj_opts *opts, int mode) {
     psdproj_opts o = opts ? *opts : default_opts(mode);
     return gemm_count_for(o);
 }
@@ -1173,7 +1206,7 @@ int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *L
                            const void *C0, const void *C0x, float alpha, float beta, float gamma, void *D, void *Dx,
                            int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream) {
     if (n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D || (C0x && !C0)) return PSDPROJ_ERR_INVALID_ARG;
-    if ((Lx == nullptr) != (Rx == nullptr)) return PSDPROJ_ERR_UNSUPPORTED;
+    if (Rx && !Lx) return PSDPROJ_ERR_UNSUPPORTED;  // one-sided: the split operand is L
     const int es[4] = {e_l, e_r, e_c0, e_d};
     for (int e : es)
         if (e < -40 || e > 40) return PSDPROJ_ERR_INVALID_ARG;

@@ -23,8 +23,9 @@ void load_env_tune_cache();
 size_t workspace_bytes_batch(const int64_t *ns, int count, int mode);
 // Workspace bytes a projection of size n in mode needs (0 for a bad mode).
 size_t workspace_bytes_for(int64_t n, int mode);
-// Number of n_p x n_p products the projection runs.
-int gemm_count_for(const psdproj_opts &o);
+// Number of n_p x n_p products the projection runs (FP16-product
+// equivalents; -1 for bad options).
+double gemm_count_for(const psdproj_opts &o);
 // Per-(device, stream) workspace pool: bytes currently held, and release.
 size_t pool_held(hipStream_t s);
 void pool_release(hipStream_t s);

@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
     L.psdproj_workspace_bytes.argtypes = [i64, c_int]
     L.psdproj_workspace_bytes.restype = ctypes.c_size_t
     L.psdproj_gemm_count.argtypes = [ctypes.POINTER(Opts), c_int]
+    L.psdproj_gemm_count.restype = ctypes.c_double
     L.psdproj_coefficients.argtypes = [c_int, ctypes.POINTER(ctypes.c_double), c_int]
     L.psdproj_release.argtypes = []
     L.psdproj_status_string.argtypes = [c_int]
@@ -92,7 +93,7 @@ def lib() -> ctypes.CDLL:
     for name in ("psdproj_gemm_timing_start", "psdproj_gemm_timing_stop",
                  "psdproj_project", "psdproj_project_ex", "psdproj_project_noalloc",
                  "psdproj_spectral_bound",
-                 "psdproj_project_batched", "psdproj_project_batched_ex", "psdproj_gemm_count",
+                 "psdproj_project_batched", "psdproj_project_batched_ex",
                  "psdproj_coefficients",
                  "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8",
                  "psdproj_admm_dual", "psdproj_admm_primal", "psdproj_autotune", "psdproj_tune_load"):
@@ -133,6 +134,8 @@ def _check_matrix(X, name="X"):
 
 
 EXPLICIT_MASK = 0x80000000
+# split_mask flag: in the masked stages only B = b A + c A^2 is split
+SPLIT_B_ONLY = 0x40000000
 
 
 def make_opts(mode="fp16", lanczos_steps=0, split_mask=None, split_final=-1, lambda_override=0.0,
@@ -255,9 +258,9 @@ def workspace_bytes(n: int, mode="fp16") -> int:
     return int(lib().psdproj_workspace_bytes(int(n), _mode(mode)))
 
 
-def gemm_count(mode="fp16", **opts) -> int:
+def gemm_count(mode="fp16", **opts) -> float:
     o = make_opts(mode=mode, **opts)
-    return int(lib().psdproj_gemm_count(ctypes.byref(o), _mode(mode)))
+    return float(lib().psdproj_gemm_count(ctypes.byref(o), _mode(mode)))
 
 
 def coefficients(mode="fp16") -> np.ndarray:

@@ -213,6 +213,67 @@ def test_sym_gemm_pair8_tile_shapes_agree(n_p):
     assert torch.equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("n_p", [256, 384])
+def test_sym_gemm_pair8_one_sided(n_p):
+    """One-sided FP8-pair product (L split, R plain FP16): L_hi R_hi on FP16
+    MFMAs plus the single cross term L_lo R_hi, two K-units per FP8 MFMA,
+    with a pair output. Checked against the FP64 product of the represented
+    values (upper triangle, mirrored: the computed triangle is L R at i <= j);
+    L rounded to FP16 instead would be several times further off."""
+    import torch
+    from gpu_util import e4m3_values, pair8_unpack
+    say("sym_gemm pair8 one-sided", n_p)
+    A = inputs.goe(n_p, 74, np.float64)
+    Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)
+    Ah = A.astype(np.float16).astype(np.float64)
+    # ||Bm|| <= ~9.25 (pair exponent 5), ||4 A + Bm A|| <= ~27 (3)
+    eL, eR, eD = 5, 7, 3
+    Lh, Lx, Lv = _pair8(Bm, eL)
+    R = to_dev(Ah.astype(np.float16))
+    D = torch.zeros_like(Lh)
+    Dx = torch.zeros(n_p, n_p, dtype=torch.uint8, device=dev())
+    P.sym_gemm_pair8(Lh, R, D, Lx=Lx, C0=R, Dx=Dx, alpha=4.0, beta=1.0, exps=(eL, eR, 0, eD))
+    torch.cuda.synchronize()
+    Dhi = D.cpu().numpy().astype(np.float64)
+    lc = pair8_unpack(Dx.cpu().numpy())
+    got = Dhi + e4m3_values()[lc] * 2.0 ** -(11 + eD)
+    ref = _sym_upper_ref(4.0 * Ah + Lv @ Ah)
+    err = rel_fro(got, ref)
+    B16 = Bm.astype(np.float16).astype(np.float64)
+    plain = rel_fro(_sym_upper_ref(4.0 * Ah + B16 @ Ah), ref)
+    say("  one-sided rel err", err, "L rounded to fp16", plain)
+    assert err < plain / 4, (err, plain)
+    np.testing.assert_array_equal(Dhi, Dhi.T)
+    tab = e4m3_values()
+    np.testing.assert_array_equal(tab[lc], tab[lc.T])
+    # R split without L split is not a supported form
+    with pytest.raises(P.PsdprojError):
+        P.sym_gemm_pair8(R, Lh, D, Rx=Lx, exps=(eR, eL, 0, 0))
+
+
+@pytest.mark.parametrize("n_p", [512, 768])
+def test_sym_gemm_pair8_one_sided_tile_shapes_agree(n_p):
+    """The one-sided product on 128 and on 256 tiles: bitwise-identical
+    results (both pair the same K-units into each FP8 MFMA)."""
+    import torch
+    say("sym_gemm pair8 one-sided tiles", n_p)
+    A = inputs.goe(n_p, 75, np.float64)
+    Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)
+    Lh, Lx, _ = _pair8(Bm, 5)
+    R = to_dev(A.astype(np.float16))
+    outs = []
+    try:
+        for tile in (128, 256):
+            P.tune("gemm_tile", tile)
+            D = torch.zeros_like(Lh)
+            P.sym_gemm_pair8(Lh, R, D, Lx=Lx, C0=R, alpha=4.0, beta=1.0, exps=(5, 7, 0, 0))
+            torch.cuda.synchronize()
+            outs.append(D.cpu())
+    finally:
+        P.tune("gemm_tile", 0)
+    assert torch.equal(outs[0], outs[1])
+
+
 def test_sym_gemm_pair8_plain_operands_pair_output():
     """Unsplit operands with a pair addend and a pair output (the product that
     feeds the first split stage)."""

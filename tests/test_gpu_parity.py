@@ -86,6 +86,29 @@ def test_fp8_pairs_against_fp16_pairs():
     assert errs["fp8_fp16_split"] <= errs["fp16"] / 8
 
 
+@pytest.mark.parametrize("mode", ["fp16_split", "fp8_fp16_split"])
+@pytest.mark.parametrize("n", [200, 777])
+def test_b_only_split_stages(mode, n):
+    """Only B = b A + c A^2 split in stages 1-4 (A = X X plain, X' = a X + B X
+    with one split operand; FP8 pairs put two 32-K units into each FP8 MFMA,
+    and n = 200 / 777 leave an odd last unit): within the oracle's tolerance,
+    and at most 0.8 of plain FP16's error against the exact projection (the
+    rounding simulation puts it at 0.5-0.6 of plain at n = 1024-4000)."""
+    X32 = inputs.goe(n, 2)
+    X = X32.astype(np.float64)
+    exact = oracle.project_exact_eigh(X)
+    say("b-only split", mode, n)
+    out, info = _run(X32, mode, split_mask=0xF | P.SPLIT_B_ONLY, split_final=0)
+    ref, _ = oracle.project_poly(X, mode, lam=info["lambda"])
+    e_poly, e_ex = rel_fro(out, ref), rel_fro(out, exact)
+    plain, _ = _run(X32, "fp16")
+    e_plain = rel_fro(plain, exact)
+    say("   vs poly", e_poly, "vs exact", e_ex, "plain fp16", e_plain)
+    np.testing.assert_array_equal(out, out.T)
+    assert e_poly <= TOL_POLY[mode]
+    assert e_ex <= 0.8 * e_plain
+
+
 @pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split"])
 def test_clustered_n1000(mode):
     X32, Q, lam = inputs.clustered(1000, 3)
@@ -310,6 +333,28 @@ def test_ksplit_tail_tiles(mode):
     out = a.cpu().numpy()
     assert rel_fro(out, ref) <= TOL_POLY[mode]
     assert rel_fro(out, ref_t.cpu().numpy()) <= 2 * TOL_POLY[mode]  # both within TOL of the oracle
+
+
+def test_ksplit_tail_tiles_b_only():
+    """K-chunked tail tiles of one-sided FP8-pair products (each chunk pairs
+    its own K-units, with an odd last one): deterministic, the batch gives the
+    same bits, and within the oracle's tolerance."""
+    import torch
+    X32 = inputs.goe(1500, 25)
+    Xg = to_dev(X32)
+    Xs = to_dev(inputs.goe(700, 26))
+    opts = dict(mode="fp8_fp16_split", split_mask=0xF | P.SPLIT_B_ONLY, split_final=0)
+    say("ksplit tail b-only")
+    forced = [("gemm_big_min", 512), ("gemm_tail_cus", 64)]
+    a, info_t = _with_tuning(forced, lambda: P.project_ex(Xg, **opts))
+    b, _ = _with_tuning(forced, lambda: P.project_ex(Xg, info=False, **opts))
+    batch, _ = _with_tuning(forced, lambda: P.project_batched_ex([Xs, Xg], info=False, **opts))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(batch[1], a)
+    info = P.read_info(info_t)
+    ref, _ = oracle.project_poly(X32.astype(np.float64), "fp8_fp16_split", lam=info["lambda"])
+    assert rel_fro(a.cpu().numpy(), ref) <= TOL_POLY["fp8_fp16_split"]
 
 
 def test_ksplit_more_chunks_than_k_tiles():

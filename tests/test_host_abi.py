@@ -57,6 +57,14 @@ def test_gemm_counts():
     assert P.gemm_count("fp16_split", split_mask=0x6, split_final=0) == 22 + 6 * 2
     assert P.gemm_count("fp8_fp16_split", split_mask=0x6, split_final=0) == 22 + 6
     assert P.gemm_count("fp8_fp16_split", split_mask=0x7F, split_final=1) == 44
+    # B-only split stages: X X and A A plain, B X one-sided (2 FP16 products
+    # with FP16 lo halves, 1.5 with FP8 pairs)
+    bo = P.SPLIT_B_ONLY
+    assert P.gemm_count("fp8_fp16_split", split_mask=0xF | bo, split_final=0) == 22 + 4 * 0.5
+    assert P.gemm_count("fp16_split", split_mask=0xF | bo, split_final=0) == 22 + 4
+    assert P.gemm_count("fp8_fp16_split", split_mask=0xF | bo, split_final=1) == 22 + 2 + 1
+    # the flag alone (no stage bits) is no split stage
+    assert P.gemm_count("fp8_fp16_split", split_mask=0x80000000 | bo, split_final=0) == 22
 
 
 def test_workspace_bytes_grow_with_n():
@@ -80,8 +88,8 @@ def test_invalid_arguments_rejected_before_device_work():
                               0.0, 1.0, 0.0, vp(16), None, None) == 1  # n_p % 128
     assert L.psdproj_sym_gemm_pair8(100, 100, vp(16), None, vp(16), None, None, None,
                                     0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 0, None) == 1  # n_p % 128
-    assert L.psdproj_sym_gemm_pair8(128, 128, vp(16), vp(16), vp(16), None, None, None,
-                                    0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 0, None) == 2  # one-sided pair
+    assert L.psdproj_sym_gemm_pair8(128, 128, vp(16), None, vp(16), vp(16), None, None,
+                                    0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 0, None) == 2  # only R split
     assert L.psdproj_sym_gemm_pair8(128, 128, vp(16), None, vp(16), None, None, None,
                                     0.0, 1.0, 0.0, vp(16), None, 0, 0, 0, 99, None) == 1  # exponent range
 
