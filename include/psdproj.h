@@ -81,8 +81,15 @@ typedef enum {
                                     instead of 3                                    */
     PSDPROJ_MODE_NS_FP16 = 6,    /* Newton-Schulz baseline of Section 4.1: 10 cubic
                                     steps (3x - x^3)/2 on FP16 MFMA, 21 products     */
-    PSDPROJ_MODE_NS_FP32 = 7     /* Newton-Schulz baseline: 15 cubic steps on FP32
+    PSDPROJ_MODE_NS_FP32 = 7,    /* Newton-Schulz baseline: 15 cubic steps on FP32
                                     MFMA, 31 products                                */
+    PSDPROJ_MODE_FP8_BF16_SPLIT = 8 /* Table 2 refined, BF16 bulk; the split products
+                                    of split_mask (default stages 1-4, as BF16) keep
+                                    a BF16 hi part and carry the correction as e4m3
+                                    codes of (M - M_hi) 2^(8 + e): BF16 hi x hi plus
+                                    both cross terms on one FP8 MFMA per 32 K, 2
+                                    product-equivalents per split product (BF16 hi+lo
+                                    pairs: 3), 34 in all                            */
 } psdproj_mode;
 
 /* split_mask flag: split only the B product of the masked stages */
@@ -437,6 +444,15 @@ int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *L
                            const void *R, const void *Rx, const void *C0, const void *C0x,
                            float alpha, float beta, float gamma, void *D, void *Dx,
                            int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream);
+
+/* psdproj_sym_gemm_pair8_bf16: the same on BF16 hi parts (the
+ * PSDPROJ_MODE_FP8_BF16_SPLIT storage): the codes hold e4m3((M - M_hi)
+ * 2^(8+e)), so that M = M_hi + 2^-(8+e) decode(codes); arguments, layout and
+ * errors as psdproj_sym_gemm_pair8. */
+int psdproj_sym_gemm_pair8_bf16(int64_t n_p, int64_t ld, const void *L, const void *Lx,
+                                const void *R, const void *Rx, const void *C0, const void *C0x,
+                                float alpha, float beta, float gamma, void *D, void *Dx,
+                                int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream);
 
 #ifdef __cplusplus
 }

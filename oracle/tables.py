@@ -125,4 +125,5 @@ MODE_TABLE = {
     "fp16_split": "f_tilde_half",
     "fp32_emu": "f_tilde_single",
     "fp8_fp16_split": "f_tilde_half",
+    "fp8_bf16_split": "f_tilde_half",
 }

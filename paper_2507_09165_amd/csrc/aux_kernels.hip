@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkI
     T *Ohi = (T *)d.hi[0];
     T *Olo = (T *)d.lo[0];
     uint8_t *Ox = (uint8_t *)d.lo[0];
-    const float ls = X8 ? __builtin_ldexpf(1.0f, 11 + e8) : 0.0f;
+    const float ls = X8 ? __builtin_ldexpf(1.0f, PairShift<T>::v + e8) : 0.0f;
     auto put = [&](int64_t i, int64_t j, float v) {
         const T hi = cvt<T>(v);
         Ohi[j * ldo + i] = hi;
@@ -760,6 +760,13 @@ hipError_t cast_x0(const BatchLaunch &B, int dtype, bool split, int e8, hipStrea
                                    e8);
             else
                 hipLaunchKernelGGL((cast_kernel<f16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
+            break;
+        case 4:  // BF16 with FP8 pairs
+            if (split)
+                hipLaunchKernelGGL((cast_kernel<bf16, true, true>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0,
+                                   0.0f, e8);
+            else
+                hipLaunchKernelGGL((cast_kernel<bf16, false>), g, blk, 0, s, B.desc, B.w_cast, B.io_tab, B.io0, 1.0f, 0);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -13,6 +13,13 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace psd {
 
+// FP8 pairs: the lo code of M is e4m3((M - M_hi) 2^(shift + e)), shift = the
+// significant bits of the hi format (the residual is at most half an ulp, 2^-shift
+// of |M|): 11 for FP16, 8 for BF16.
+template <typename T> struct PairShift { static constexpr int v = 0; };  // no FP8 pairs
+template <> struct PairShift<f16> { static constexpr int v = 11; };
+template <> struct PairShift<bf16> { static constexpr int v = 8; };
+
 // Device-resident scalar block of one projection (all FP64 so that the bound
 // never loses digits). Written by the norm/Lanczos kernels, read by the cast
 // and final kernels; never copied to the host inside a projection.

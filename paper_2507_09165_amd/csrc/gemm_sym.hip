@@ -117,7 +117,7 @@ int gemm_tail_cus(int device_cus) {
 static std::atomic<int> g_split_big{3};
 bool gemm_split_big(int dtype) {
     if (g_tile_override == 128) return false;
-    if (dtype == DT_F16X8) return (g_split_big & 2) != 0;
+    if (dtype == DT_F16X8 || dtype == DT_BF16X8) return (g_split_big & 2) != 0;
     return dtype != DT_F32 && (g_split_big & 1) != 0;
 }
 void gemm_set_split_big(int mask) {
@@ -220,6 +220,7 @@ hipError_t gemm_sym_launch(const GemmArgs &g, int dtype, int epi, bool ls, bool 
         case DT_F16: PSD_EPI(DT_F16)
         case DT_BF16: PSD_EPI(DT_BF16)
         case DT_F16X8: PSD_EPI(DT_F16X8)
+        case DT_BF16X8: PSD_EPI(DT_BF16X8)
     }
 #undef PSD_EPI
     return hipErrorInvalidValue;

@@ -6,9 +6,9 @@
 
 namespace psd {
 
-// DT_F16X8: FP16 work matrices whose split slots carry the e4m3 lo codes of
-// an FP8 pair (see lo8_index) instead of FP16 lo halves.
-enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F16X8 = 3 };
+// DT_F16X8 / DT_BF16X8: FP16 / BF16 work matrices whose split slots carry the
+// e4m3 lo codes of an FP8 pair (see lo8_index) instead of lo halves.
+enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F16X8 = 3, DT_BF16X8 = 4 };
 enum Epi { EPI_STORE = 0, EPI_STORE_SPLIT = 1, EPI_FINAL = 2 };
 
 // Output tile edge; work matrices are zero-padded to a multiple of it.

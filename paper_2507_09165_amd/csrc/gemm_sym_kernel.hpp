@@ -73,13 +73,19 @@ __device__ __forceinline__ void mma_x8(f32x16 &acc, u32x4 a0, u32x4 a1, u32x4 b0
 // order), divided by sc (v_cvt_scalef32_pk_fp8_f16 divides by its scale; sc
 // = 2^-e gives the codes of v 2^e), packed in the byte order of the pair's lo
 // codes.
+template <typename T>
 __device__ __forceinline__ u32x4 hi8_codes(u32x4 h0, u32x4 h1, float sc) {
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef T h2 __attribute__((ext_vector_type(2)));
     typedef short s2 __attribute__((ext_vector_type(2)));
     auto pk = [&](uint32_t lo_pair, uint32_t hi_pair) -> uint32_t {
         s2 w = {0, 0};
-        w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, lo_pair), sc, false);
-        w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, hi_pair), sc, true);
+        if constexpr (__is_same(T, f16)) {
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, lo_pair), sc, false);
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(w, __builtin_bit_cast(h2, hi_pair), sc, true);
+        } else {
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(w, __builtin_bit_cast(h2, lo_pair), sc, false);
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(w, __builtin_bit_cast(h2, hi_pair), sc, true);
+        }
         return __builtin_bit_cast(uint32_t, w);
     };
     return u32x4{pk(h0.x, h0.y), pk(h0.z, h0.w), pk(h1.x, h1.y), pk(h1.z, h1.w)};
@@ -163,7 +169,7 @@ __device__ __forceinline__ void wait_lgkmcnt() {
 // partial round of 256 tiles.
 template <typename T, bool LS, bool RS, int EPI, int BM, int ROWB, int NST, bool X8, int KS>
 __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
-    static_assert(!X8 || (sizeof(T) == 2 && (LS || !RS)), "FP8 pairs: FP16 hi, L split whenever R is");
+    static_assert(!X8 || (sizeof(T) == 2 && (LS || !RS)), "FP8 pairs: FP16 or BF16 hi, L split whenever R is");
     constexpr bool PAIR8 = X8 && LS;          // FP8 cross terms in the main loop
     constexpr bool ONE8 = PAIR8 && !RS;       // one-sided: L_lo R_hi only
     constexpr bool COMB = LS && RS && !X8 && BM == 128;
@@ -347,7 +353,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         constexpr int NFP = PAIR8 ? (RS ? 6 : 5) : NLP + NRP;
         typedef u32x4 Frag[NFP][MI];
         // E8M0 scale codes 2^(c - 127), replicated into every byte
-        const int sa8 = PAIR8 ? (int)((uint32_t)(127 - 11 - g.es_l) * 0x01010101u) : 0;
+        constexpr int PSH = X8 ? PairShift<T>::v : 0;  // bits of the hi format
+        const int sa8 = PAIR8 ? (int)((uint32_t)(127 - PSH - g.es_l) * 0x01010101u) : 0;
         const int sb8 = PAIR8 ? (int)((uint32_t)(127 - g.es_r) * 0x01010101u) : 0;
         const float cva = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_l) : 0.0f;  // hi-code conversion scales
         const float cvb = PAIR8 ? __builtin_ldexpf(1.0f, -g.es_r) : 0.0f;
@@ -501,8 +508,8 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
                         u32x4 ha[MI], hb[MI];
 #pragma unroll
                         for (int m = 0; m < MI; ++m) {
-                            if constexpr (RS) ha[m] = hi8_codes(f[0][m], f[1][m], cva);
-                            hb[m] = hi8_codes(f[3][m], f[4][m], cvb);
+                            if constexpr (RS) ha[m] = hi8_codes<T>(f[0][m], f[1][m], cva);
+                            hb[m] = hi8_codes<T>(f[3][m], f[4][m], cvb);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                         wait_lgkmcnt<0>();
@@ -641,8 +648,9 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
         const T *C0lo = (g.sc0 >= 0 && g.c0_split) ? (const T *)dm.lo[g.sc0] : nullptr;
         const float c0lo = 1.0f / Elt<T>::kSplit;
         // FP8 pairs: code scales of the addend and of the output slot
-        const float c0x = X8 ? __builtin_ldexpf(1.0f, -(11 + g.es_c0)) : 0.0f;
-        const float dls = X8 ? __builtin_ldexpf(1.0f, 11 + g.es_d) : 0.0f;
+        constexpr int PSE = X8 ? PairShift<T>::v : 0;
+        const float c0x = X8 ? __builtin_ldexpf(1.0f, -(PSE + g.es_c0)) : 0.0f;
+        const float dls = X8 ? __builtin_ldexpf(1.0f, PSE + g.es_d) : 0.0f;
         uint8_t *Dx = (uint8_t *)dm.lo[g.sd];
         typedef T t4 __attribute__((ext_vector_type(4)));
 #pragma clang loop unroll(full)
@@ -763,25 +771,25 @@ static hipError_t launch_bm(const GemmArgs &g, int64_t ntiles, hipStream_t s, in
     return hipGetLastError();
 }
 
-template <int EPI>
+template <typename T, int EPI>
 static hipError_t launch_x8(const GemmArgs &g, bool ls, bool rs, int bm, int64_t ntiles, hipStream_t s, int ks) {
     if (ls && rs) {
         switch (bm) {
-            case 256: return launch_bm<f16, true, true, EPI, 256, true>(g, ntiles, s, ks);
-            case 128: return launch_bm<f16, true, true, EPI, 128, true>(g, ntiles, s, ks);
+            case 256: return launch_bm<T, true, true, EPI, 256, true>(g, ntiles, s, ks);
+            case 128: return launch_bm<T, true, true, EPI, 128, true>(g, ntiles, s, ks);
         }
         return hipErrorInvalidValue;
     }
     if (ls) {
         switch (bm) {
-            case 256: return launch_bm<f16, true, false, EPI, 256, true>(g, ntiles, s, ks);
-            case 128: return launch_bm<f16, true, false, EPI, 128, true>(g, ntiles, s, ks);
+            case 256: return launch_bm<T, true, false, EPI, 256, true>(g, ntiles, s, ks);
+            case 128: return launch_bm<T, true, false, EPI, 128, true>(g, ntiles, s, ks);
         }
         return hipErrorInvalidValue;
     }
     switch (bm) {
-        case 256: return launch_bm<f16, false, false, EPI, 256, true>(g, ntiles, s, ks);
-        case 128: return launch_bm<f16, false, false, EPI, 128, true>(g, ntiles, s, ks);
+        case 256: return launch_bm<T, false, false, EPI, 256, true>(g, ntiles, s, ks);
+        case 128: return launch_bm<T, false, false, EPI, 128, true>(g, ntiles, s, ks);
     }
     return hipErrorInvalidValue;
 }
@@ -819,7 +827,8 @@ hipError_t gemm_launch_part(const GemmArgs &g, bool ls, bool rs, int bm, int64_t
         return launch_split<bf16, EPI>(g, ls, rs, bm, ntiles, s, ks);
     } else {
         if (rs && !ls) return hipErrorInvalidValue;  // one-sided pairs: the split operand on the left
-        return launch_x8<EPI>(g, ls, rs, bm, ntiles, s, ks);
+        if constexpr (DT == DT_BF16X8) return launch_x8<bf16, EPI>(g, ls, rs, bm, ntiles, s, ks);
+        else return launch_x8<f16, EPI>(g, ls, rs, bm, ntiles, s, ks);
     }
 }
 

@@ -124,6 +124,8 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
             tab = kTildeSingle; T = 10; nres = kSingleRescaled; res = kSingleRescale; p.dtype = DT_F16; break;
         case PSDPROJ_MODE_FP8_FP16_SPLIT:
             tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_F16X8; break;
+        case PSDPROJ_MODE_FP8_BF16_SPLIT:
+            tab = kTildeHalf; T = 7; nres = kHalfRescaled; res = kHalfRescale; p.dtype = DT_BF16X8; break;
         case PSDPROJ_MODE_NS_FP16:
         case PSDPROJ_MODE_NS_FP32:
             // Newton-Schulz baseline: x <- (3 x - x^3) / 2, no stage rescale
@@ -159,8 +161,10 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
     p.T = T + o.adaptive_extra;
     p.adaptive = o.adaptive_tol > 0.0 && o.adaptive_extra > 0;
     p.adapt_from = T;
-    if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT || o.mode == PSDPROJ_MODE_BF16) {
-        const uint32_t def = o.mode == PSDPROJ_MODE_BF16 ? kDefaultSplitMaskBf16 : kDefaultSplitMask;
+    if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT || o.mode == PSDPROJ_MODE_BF16 ||
+        o.mode == PSDPROJ_MODE_FP8_BF16_SPLIT) {
+        const bool bf = o.mode == PSDPROJ_MODE_BF16 || o.mode == PSDPROJ_MODE_FP8_BF16_SPLIT;
+        const uint32_t def = bf ? kDefaultSplitMaskBf16 : kDefaultSplitMask;
         const uint32_t m = (o.split_mask & kExplicitMask) ? (o.split_mask & ~kExplicitMask)
                                                           : (o.split_mask ? o.split_mask : def);
         p.split_mask = m & ((1u << T) - 1);
@@ -615,7 +619,8 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     int cur = 0;
     bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
     double *adapt_part = (double *)(b + P.off_adapt);
-    const int check_dt = p.dtype == DT_F16X8 ? DT_F16 : p.dtype;  // unsplit FP8-pair storage is FP16
+    // unsplit FP8-pair storage is FP16 / BF16
+    const int check_dt = p.dtype == DT_F16X8 ? DT_F16 : p.dtype == DT_BF16X8 ? DT_BF16 : p.dtype;
     // adaptive depth: after stage t (its iterate in slot sn), record the slot
     // once the designed stages are done, and test the change of every
     // skippable stage
@@ -917,8 +922,9 @@ double gemm_count_for(const psdproj_opts &o) {
     // FP8 pair product is one FP16 product plus one FP8 product of twice the K
     // at twice the rate (one-sided: of the same K, 1.5 in all)
     if (p.cubic) return 2 * p.T + 1;
-    const double pair = p.dtype == DT_F16X8 ? 2.0 : 3.0;
-    const double one = p.dtype == DT_F16X8 ? 1.5 : 2.0;
+    const bool x8 = p.dtype == DT_F16X8 || p.dtype == DT_BF16X8;
+    const double pair = x8 ? 2.0 : 3.0;
+    const double one = x8 ? 1.5 : 2.0;
     double g = 0;
     bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
     for (int t = 0; t < p.T; ++t) {
@@ -1211,6 +1217,18 @@ int psdproj_sym_gemm_pair8(int64_t n_p, int64_t ld, const void *L, const void *L
     for (int e : es)
         if (e < -40 || e > 40) return PSDPROJ_ERR_INVALID_ARG;
     return sym_gemm_impl(DT_F16X8, n_p, ld, L, Lx, R, Rx, C0, C0x, alpha, beta, gamma, D, Dx, es,
+                         (hipStream_t)stream);
+}
+
+int psdproj_sym_gemm_pair8_bf16(int64_t n_p, int64_t ld, const void *L, const void *Lx, const void *R, const void *Rx,
+                                const void *C0, const void *C0x, float alpha, float beta, float gamma, void *D,
+                                void *Dx, int e_l, int e_r, int e_c0, int e_d, psdproj_stream_t stream) {
+    if (n_p <= 0 || n_p % kTile || ld < n_p || !L || !R || !D || (C0x && !C0)) return PSDPROJ_ERR_INVALID_ARG;
+    if (Rx && !Lx) return PSDPROJ_ERR_UNSUPPORTED;
+    const int es[4] = {e_l, e_r, e_c0, e_d};
+    for (int e : es)
+        if (e < -40 || e > 40) return PSDPROJ_ERR_INVALID_ARG;
+    return sym_gemm_impl(DT_BF16X8, n_p, ld, L, Lx, R, Rx, C0, C0x, alpha, beta, gamma, D, Dx, es,
                          (hipStream_t)stream);
 }
 

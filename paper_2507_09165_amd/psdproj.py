@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsdproj.so")
 
 MODES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "fp32_emu": 4, "fp8_fp16_split": 5,
-         "ns_fp16": 6, "ns_fp32": 7}
+         "ns_fp16": 6, "ns_fp32": 7, "fp8_bf16_split": 8}
 DTYPES = {"fp32": 0, "fp16": 1, "bf16": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory",
@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     L.psdproj_sym_gemm_pair8.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float, vp, vp, c_int, c_int, c_int, c_int, vp]
+    L.psdproj_sym_gemm_pair8_bf16.argtypes = L.psdproj_sym_gemm_pair8.argtypes
     L.psdproj_autotune.argtypes = [c_int, ctypes.POINTER(i64), c_int, ctypes.c_char_p, vp]
     L.psdproj_tune_load.argtypes = [ctypes.c_char_p]
     L.psdproj_admm_dual.argtypes = [i64, i64, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp]
@@ -95,7 +96,7 @@ def lib() -> ctypes.CDLL:
                  "psdproj_spectral_bound",
                  "psdproj_project_batched", "psdproj_project_batched_ex",
                  "psdproj_coefficients",
-                 "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8",
+                 "psdproj_release", "psdproj_sym_gemm", "psdproj_sym_gemm_pair8", "psdproj_sym_gemm_pair8_bf16",
                  "psdproj_admm_dual", "psdproj_admm_primal", "psdproj_autotune", "psdproj_tune_load"):
         getattr(L, name).restype = c_int
     _lib = L
@@ -308,16 +309,18 @@ def sym_gemm(dtype, L, R, D, Llo=None, Rlo=None, C0=None, C0lo=None, Dlo=None,
 
 def sym_gemm_pair8(L, R, D, Lx=None, Rx=None, C0=None, C0x=None, Dx=None, alpha=0.0, beta=1.0,
                    gamma=0.0, exps=(0, 0, 0, 0), stream=None):
-    """D = alpha C0 + beta L R + gamma I on FP16 work matrices whose split
-    parts are FP8 pair codes (uint8 tensors of n_p * ld bytes in the tiled
-    layout documented in psdproj.h); exps are the pair exponents of
-    (L, R, C0, D)."""
+    """D = alpha C0 + beta L R + gamma I on FP16 (or, for bfloat16 tensors,
+    BF16) work matrices whose split parts are FP8 pair codes (uint8 tensors of
+    n_p * ld bytes in the tiled layout documented in psdproj.h); exps are the
+    pair exponents of (L, R, C0, D)."""
+    import torch
     n_p = L.shape[0]
     ld = L.stride(0)
     e = [int(v) for v in exps]
-    _check(lib().psdproj_sym_gemm_pair8(n_p, ld, _ptr(L), _ptr(Lx), _ptr(R), _ptr(Rx), _ptr(C0), _ptr(C0x),
-                                        float(alpha), float(beta), float(gamma), _ptr(D), _ptr(Dx),
-                                        e[0], e[1], e[2], e[3], _stream(stream)), "psdproj_sym_gemm_pair8")
+    name = "psdproj_sym_gemm_pair8_bf16" if L.dtype == torch.bfloat16 else "psdproj_sym_gemm_pair8"
+    _check(getattr(lib(), name)(n_p, ld, _ptr(L), _ptr(Lx), _ptr(R), _ptr(Rx), _ptr(C0), _ptr(C0x),
+                                float(alpha), float(beta), float(gamma), _ptr(D), _ptr(Dx),
+                                e[0], e[1], e[2], e[3], _stream(stream)), name)
     return D
 
 

@@ -23,7 +23,7 @@ def _single(X, mode):
     return out, info_t
 
 
-@pytest.mark.parametrize("mode", ["bf16", "fp16", "fp32", "fp16_split", "fp8_fp16_split"])
+@pytest.mark.parametrize("mode", ["bf16", "fp16", "fp32", "fp16_split", "fp8_fp16_split", "fp8_bf16_split"])
 def test_batched_mixed_sizes_equal_single(mode):
     import torch
     sizes = [1, 32, 33, 100, 128, 257, 640, 1024, 1600]
@@ -36,22 +36,24 @@ def test_batched_mixed_sizes_equal_single(mode):
         assert torch.equal(a, b), n
 
 
-def test_batched_blocks_match_oracle():
+@pytest.mark.parametrize("mode", ["bf16", "fp8_bf16_split"])
+def test_batched_blocks_match_oracle(mode):
     """The batched workload (256 GOE blocks, n log-uniform in [32, 1024],
-    seed 7, BF16 with its default split): every block against the FP64 oracle
-    with the bound the batch computed for it, at the half-precision target."""
+    seed 7, BF16 with its default split: BF16 hi+lo pairs, or a BF16 hi part
+    with FP8 lo codes): every block against the FP64 oracle with the bound the
+    batch computed for it, at the half-precision target."""
     import torch
     sizes = inputs.batch_sizes(256, 7)
     blocks = inputs.batch_blocks(sizes, 7)
-    say("batched C4, 256 blocks")
+    say("batched C4, 256 blocks", mode)
     Xs = [to_dev(B) for B in blocks]
-    outs, info_t = P.project_batched_ex(Xs, mode="bf16")
+    outs, info_t = P.project_batched_ex(Xs, mode=mode)
     torch.cuda.synchronize()
     infos = P.read_infos(info_t)
     worst = 0.0
     for k, (B, o, info) in enumerate(zip(blocks, outs, infos)):
         assert info["nonfinite"] == 0 and info["fallback"] == 0
-        ref, _ = oracle.project_poly(B.astype(np.float64), "bf16", lam=info["lambda"])
+        ref, _ = oracle.project_poly(B.astype(np.float64), mode, lam=info["lambda"])
         e = rel_fro(o.cpu().numpy(), ref)
         worst = max(worst, e)
         assert e <= 5e-3, (k, B.shape[0], e)

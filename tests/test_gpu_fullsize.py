@@ -25,7 +25,7 @@ from gpu_util import rel_fro, rocsolver_eigh64, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL_POLY = {"fp16": 5e-3, "bf16": 5e-3, "fp16_split": 5e-3, "fp8_fp16_split": 5e-3}
+TOL_POLY = {"fp16": 5e-3, "bf16": 5e-3, "fp16_split": 5e-3, "fp8_fp16_split": 5e-3, "fp8_bf16_split": 5e-3}
 
 
 def _max_abs_bound(ref, tol):
@@ -130,7 +130,7 @@ def test_n4096_fp16_bf16(case):
     X32 = inputs.goe(n, 2) if case == "goe" else inputs.clustered(n, 3)[0].astype(np.float32)
     X = to_dev(X32)
     X64 = X32.astype(np.float64)
-    for mode in ("fp16", "bf16"):
+    for mode in ("fp16", "bf16", "fp8_bf16_split"):
         out, info_t = P.project_ex(X, mode=mode)
         torch.cuda.synchronize()
         info = P.read_info(info_t)

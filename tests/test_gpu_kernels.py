@@ -140,15 +140,15 @@ def test_sym_gemm_tile_shapes_agree(dt, split):
         assert torch.equal(outs[0][1], outs[1][1])
 
 
-def _pair8(M, e):
-    """FP16 hi and the FP8 pair codes of a symmetric FP64 matrix; returns the
-    device tensors and the value the pair represents."""
+def _pair8(M, e, dt="fp16"):
+    """FP16 (or BF16) hi and the FP8 pair codes of a symmetric FP64 matrix;
+    returns the device tensors and the value the pair represents."""
     from gpu_util import e4m3_encode, e4m3_values, pair8_pack
-    hi = M.astype(np.float16)
-    hi64 = hi.astype(np.float64)
-    lc = e4m3_encode((M - hi64) * 2.0 ** (11 + e))
-    val = hi64 + e4m3_values()[lc] * 2.0 ** -(11 + e)
-    return to_dev(hi), to_dev(pair8_pack(lc)), val
+    shift = 11 if dt == "fp16" else 8  # significant bits of the hi format
+    hi_t, hi64 = _rounded(M, dt)
+    lc = e4m3_encode((M - hi64) * 2.0 ** (shift + e))
+    val = hi64 + e4m3_values()[lc] * 2.0 ** -(shift + e)
+    return hi_t.to(dev()), to_dev(pair8_pack(lc)), val
 
 
 @pytest.mark.parametrize("n_p", [256, 384])
@@ -185,6 +185,40 @@ def test_sym_gemm_pair8(n_p):
     np.testing.assert_array_equal(Dhi, Dhi.T)
     tab = e4m3_values()  # compare decoded codes: -0 and +0 are one value
     np.testing.assert_array_equal(tab[lc], tab[lc.T])
+
+
+@pytest.mark.parametrize("n_p", [256, 384])
+def test_sym_gemm_pair8_bf16(n_p):
+    """FP8 pairs on a BF16 hi part (codes of (M - M_hi) 2^(8+e)): BF16 hi x hi
+    plus both cross terms on the e4m3 MFMA, pair addend and pair output,
+    against the FP64 product of the represented values; several times closer
+    than BF16 storage alone."""
+    import torch
+    from gpu_util import e4m3_values, pair8_unpack
+    say("sym_gemm pair8 bf16", n_p)
+    A = inputs.goe(n_p, 76, np.float64)
+    Bm = A @ A * 2.5 - 0.75 * np.eye(n_p)
+    eL, eR, eC, eD = 7, 5, 7, 3
+    Lh, Lx, Lv = _pair8(A, eL, "bf16")
+    Rh, Rx, Rv = _pair8(Bm, eR, "bf16")
+    Ch, Cx, Cv = _pair8(A, eC, "bf16")
+    D = torch.zeros_like(Lh)
+    Dx = torch.zeros(n_p, n_p, dtype=torch.uint8, device=dev())
+    P.sym_gemm_pair8(Lh, Rh, D, Lx=Lx, Rx=Rx, C0=Ch, C0x=Cx, Dx=Dx, alpha=0.5, beta=-1.25,
+                     exps=(eL, eR, eC, eD))
+    torch.cuda.synchronize()
+    Dhi = D.to(torch.float64).cpu().numpy()
+    lc = pair8_unpack(Dx.cpu().numpy())
+    got = Dhi + e4m3_values()[lc] * 2.0 ** -(8 + eD)
+    ref = 0.5 * Cv + -1.25 * (Lv @ Rv)
+    err = rel_fro(got, ref)
+    _, A16 = _rounded(A, "bf16")
+    _, B16 = _rounded(Bm, "bf16")
+    plain = rel_fro(0.5 * A16 - 1.25 * (A16 @ B16), ref)
+    say("  pair8 bf16 rel err", err, "plain bf16 operands", plain)
+    assert err < plain / 3, (err, plain)
+    assert err < 2e-3, err
+    np.testing.assert_array_equal(Dhi, Dhi.T)
 
 
 @pytest.mark.parametrize("n_p", [512, 768])

@@ -19,6 +19,7 @@ from gpu_util import dev, rel_fro, say, to_dev
 pytestmark = pytest.mark.gpu
 
 TOL_POLY = {"fp32": 1e-5, "fp32_emu": 1e-5, "fp16": 5e-3, "fp16_split": 5e-3, "fp8_fp16_split": 5e-3,
+            "fp8_bf16_split": 5e-3,
             "bf16": 5e-3, "ns_fp16": 5e-3, "ns_fp32": 1e-5}
 
 
@@ -55,7 +56,8 @@ def test_c1_fp32_n256():
     assert rel_fro(out, exact) < 2e-5
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp32", "fp32_emu"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp8_bf16_split", "fp32",
+                                  "fp32_emu"])
 @pytest.mark.parametrize("n", [200, 777])
 def test_goe_ragged(mode, n):
     X32 = inputs.goe(n, 2)
@@ -109,7 +111,7 @@ def test_b_only_split_stages(mode, n):
     assert e_ex <= 0.8 * e_plain
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp8_bf16_split"])
 def test_clustered_n1000(mode):
     X32, Q, lam = inputs.clustered(1000, 3)
     exact = oracle.project_spectral(Q, lam, lambda l: np.maximum(l, 0.0))
@@ -234,6 +236,25 @@ def test_forced_fallback_uses_frobenius():
     assert rel_fro(out, ref) < 1e-5
 
 
+def test_fp8_bf16_pairs_against_bf16_pairs():
+    """BF16 with FP8 lo codes in stages 1-4 against BF16 hi+lo pairs in the
+    same stages: the e4m3 code (2^-4) of a 2^-8 residual leaves the operand at
+    about 2^-12, far below the plain BF16 stages 5-7, so both land at the same
+    error (a rounding simulation: 3.16e-3 against 3.14e-3 at n = 1024), well
+    under plain BF16."""
+    X32 = inputs.goe(777, 2)
+    X = X32.astype(np.float64)
+    exact = oracle.project_exact_eigh(X)
+    errs = {}
+    for name, mode, opts in (("plain", "bf16", dict(split_mask=0)), ("pairs", "bf16", {}),
+                             ("fp8", "fp8_bf16_split", {})):
+        out, info = _run(X32, mode, **opts)
+        errs[name] = rel_fro(out, exact)
+    say("  bf16 errors vs exact", errs)
+    assert errs["fp8"] <= 1.25 * errs["pairs"]
+    assert errs["fp8"] <= errs["plain"] / 2
+
+
 def test_bf16_split_default_against_plain():
     """Ablation of the BF16 default: plain BF16 storage at every stage (split
     mask given explicitly as 0) misses the half-precision target, the default
@@ -269,7 +290,7 @@ def test_batched_equals_single():
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp8_fp16_split"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp8_fp16_split", "fp8_bf16_split"])
 def test_mixed_tile_sizes_bitwise_equal(mode):
     """Plain products on whole rounds of 256 tiles plus a tail of 128 tiles
     (forced at a small size: 256 tiles from n = 512, a tail rule for 8 CUs)
@@ -308,7 +329,7 @@ def _with_tuning(settings, fn):
         P.tune("gemm_tile", 0)
 
 
-@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp32_emu"])
+@pytest.mark.parametrize("mode", ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp8_bf16_split", "fp32_emu"])
 def test_ksplit_tail_tiles(mode):
     """Tail tiles cut into K-chunks (forced: 256 tiles from n = 512 and a tail
     rule for 64 CUs, so all 21 tiles of n = 1500 form the tail, 3 chunks

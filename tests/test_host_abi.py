@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("mode", ["fp32", "fp16", "bf16", "fp16_split", "fp32_emu", "fp8_fp16_split",
-                                  "ns_fp16", "ns_fp32"])
+                                  "ns_fp16", "ns_fp32", "fp8_bf16_split"])
 def test_library_coefficients_match_oracle(mode):
     lib_rows = P.coefficients(mode)
     ora_rows = oracle.stage_rows(mode)
@@ -63,6 +63,9 @@ def test_gemm_counts():
     assert P.gemm_count("fp8_fp16_split", split_mask=0xF | bo, split_final=0) == 22 + 4 * 0.5
     assert P.gemm_count("fp16_split", split_mask=0xF | bo, split_final=0) == 22 + 4
     assert P.gemm_count("fp8_fp16_split", split_mask=0xF | bo, split_final=1) == 22 + 2 + 1
+    # BF16 with FP8 pairs: stages 1-4 split by default like BF16, 2 per split product
+    assert P.gemm_count("fp8_bf16_split") == 4 * 3 * 2 + 3 * 3 + 1 == 34
+    assert P.gemm_count("fp8_bf16_split", split_mask=0x6, split_final=0) == 22 + 6
     # the flag alone (no stage bits) is no split stage
     assert P.gemm_count("fp8_fp16_split", split_mask=0x80000000 | bo, split_final=0) == 22
 
