@@ -199,6 +199,16 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
  * leading dimensions and device pointers). Matrices are independent; each
  * result equals the one psdproj_project gives for that matrix alone.
  *
+ * Small matrices: in the half-precision modes (FP16, BF16, FP16_SPLIT,
+ * FP8_FP16_SPLIT, FP8_BF16_SPLIT) without deflation, adaptive depth or
+ * split_mask's B-only flag, a matrix of order n <= 128 (tuning key
+ * "small_max") runs all of Algorithm 2 in one workgroup: every such matrix of
+ * a call in one launch, which a batched call runs on a side stream of the
+ * caller's stream beside the launch sequence of its larger matrices (forked
+ * and joined by events; under capture before the side stream exists, on the
+ * caller's stream). The rule depends only on (n, mode, options), so a matrix
+ * takes the same path alone and in any batch.
+ *
  * Graph capture (this call and psdproj_project / _ex / _batched_ex): a call
  * with the sizes, mode and options of the previous call on the same stream
  * issues kernel launches only and may be captured into a HIP graph; make the
@@ -263,7 +273,9 @@ const char *psdproj_status_string(int status);
  * device's); "work_ld_pad" = elements added to the leading dimension of work
  * matrices whose padded order n_p >= 2048 is a multiple of 1024 (default 128;
  * multiple of 64; synchronises the device); "gemm_block" = H * 256 + W sets the blocking of the GEMM tile
- * schedule (H tile rows x W tile columns per block). Plans are rebuilt after a
+ * schedule (H tile rows x W tile columns per block); "small_max" = largest
+ * order of the one-workgroup path of small matrices (0..128, default 128; 0
+ * sends every matrix through the launch sequence). Plans are rebuilt after a
  * change. Returns PSDPROJ_ERR_NOT_FOUND for unknown keys. */
 int psdproj_tune(const char *key, int64_t value);
 

@@ -19,6 +19,7 @@
 
 #include "aux_kernels.hpp"
 #include "common.hpp"
+#include "lanczos_dev.hpp"
 
 namespace psd {
 
@@ -119,16 +120,6 @@ __global__ __launch_bounds__(256) void cast_kernel(const MatDesc *D, const WorkI
 // ---------------------------------------------------------------------------
 // Lanczos
 // ---------------------------------------------------------------------------
-// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
-// z_i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15); v_i = 2 (z_i >> 11) 2^-53 - 1.
-__device__ __forceinline__ double start_entry(uint64_t i, uint64_t seed) {
-    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z = z ^ (z >> 31);
-    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
-}
-
 // Input vector of a symmetric matvec.
 enum SymvSrc { SRC_V = 0, SRC_U = 1, SRC_W = 2, SRC_QHAT = 3 };
 // Output vector of the reduction.
@@ -351,7 +342,7 @@ __global__ __launch_bounds__(kVecThreads) void symv_reduce_kernel(const MatDesc 
 }
 
 __global__ void scal_init_kernel(const MatDesc *D) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !D[blockIdx.x].fused) {
         Scalars z = {};
         *D[blockIdx.x].scal = z;
     }
@@ -466,28 +457,10 @@ __global__ __launch_bounds__(256) void lz_next_kernel(const MatDesc *D, const Wo
     }
 }
 
-// Number of eigenvalues of the k x k symmetric tridiagonal (al, be) below x
-// (Sylvester inertia of the LDL^T factorisation of T - x I).
-__device__ __forceinline__ int sturm_count(const double *al, const double *be, int k, double x, double tiny) {
-    int cnt = 0;
-    double d = al[0] - x;
-    if (d == 0.0) d = -tiny;
-    cnt += d < 0.0;
-    for (int i = 1; i < k; ++i) {
-        d = al[i] - x - be[i - 1] * be[i - 1] / d;
-        if (d == 0.0) d = -tiny;
-        cnt += d < 0.0;
-    }
-    return cnt;
-}
-
-// Largest eigenpair of the k x k tridiagonal T (alpha, beta) of the Lanczos
-// run (k <= KM). sigma: multisection of the Gershgorin interval on the Sturm
-// count, one wave evaluating 64 shifts per round. s: inverse iteration on
-// T - sigma I with a partially pivoted tridiagonal LU (one thread; loops are
-// unrolled to KM with guards so the arrays stay in registers).
+// Largest Ritz pair of the matrix's Lanczos run into its Scalars.
 template <int KM>
 __global__ __launch_bounds__(64) void lz_ritz_kernel(const MatDesc *D) {
+    if (D[blockIdx.x].fused) return;
     Scalars *scal = D[blockIdx.x].scal;
     const int lane = threadIdx.x;
     const int k = scal->k;
@@ -498,102 +471,7 @@ __global__ __launch_bounds__(64) void lz_ritz_kernel(const MatDesc *D) {
         be[lane] = lane < k - 1 ? scal->beta[lane] : 0.0;
     }
     __syncthreads();
-    if (lane == 0) {
-        double lo = 0.0, hi = 0.0;
-        for (int i = 0; i < k; ++i) {
-            const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
-            lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
-            hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
-        }
-        lo_hi[0] = lo;
-        lo_hi[1] = hi;
-    }
-    __syncthreads();
-    double lo = lo_hi[0], hi = lo_hi[1];
-    const double scale_t = fmax(fabs(lo), fabs(hi));
-    const double tiny = 1e-300 + 1e-30 * scale_t;
-    // invariant: count(lo) < k (sigma >= lo), count(hi) == k (sigma < hi)
-    hi = hi + 1e-15 * scale_t + tiny;
-    for (int it = 0; it < 40; ++it) {
-        if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi))) || !(hi > lo)) break;
-        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-        const int all_below = sturm_count(al, be, k, x, tiny) == k;
-        const unsigned long long m = __ballot(all_below);  // lanes whose shift is above sigma
-        const int f = m ? __ffsll((long long)m) - 1 : 64;
-        const double nlo = f == 0 ? lo : lo + (hi - lo) * (double)f / 65.0;
-        const double nhi = f == 64 ? hi : lo + (hi - lo) * (double)(f + 1) / 65.0;
-        lo = nlo;
-        hi = nhi;
-    }
-    if (lane != 0) return;
-    const double sigma = 0.5 * (lo + hi);
-    scal->sigma = sigma;
-    // LU of T - sigma I with partial pivoting: rows i, i+1 may swap; U has two
-    // superdiagonals (du, du2); dl holds the multipliers.
-    double d[KM], du[KM], du2[KM], dl[KM], x[KM];
-    bool sw[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) {
-        d[i] = i < k ? al[i] - sigma : 1.0;
-        du[i] = i < k - 1 ? be[i] : 0.0;
-        dl[i] = i < k - 1 ? be[i] : 0.0;
-        du2[i] = 0.0;
-        sw[i] = false;
-        x[i] = i < k ? 1.0 : 0.0;
-    }
-    const double eps_p = 1e-15 * (scale_t > 0.0 ? scale_t : 1.0);
-#pragma unroll
-    for (int i = 0; i < KM - 1; ++i) {
-        if (i < k - 1) {
-            if (fabs(d[i]) >= fabs(dl[i])) {
-                if (fabs(d[i]) < eps_p) d[i] = d[i] < 0.0 ? -eps_p : eps_p;
-                const double f = dl[i] / d[i];
-                dl[i] = f;
-                d[i + 1] -= f * du[i];
-            } else {
-                const double f = d[i] / dl[i];
-                d[i] = dl[i];
-                dl[i] = f;
-                const double t = du[i];
-                du[i] = d[i + 1];
-                d[i + 1] = t - f * d[i + 1];
-                if (i < k - 2) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
-                sw[i] = true;
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < KM; ++i)
-        if (i == k - 1 && fabs(d[i]) < eps_p) d[i] = d[i] < 0.0 ? -eps_p : eps_p;
-    for (int it = 0; it < 3; ++it) {
-#pragma unroll
-        for (int i = 0; i < KM - 1; ++i) {  // L^-1 P
-            if (i < k - 1) {
-                if (sw[i]) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
-                x[i + 1] -= dl[i] * x[i];
-            }
-        }
-#pragma unroll
-        for (int i = KM - 1; i >= 0; --i) {  // U^-1
-            if (i < k) {
-                double v = x[i];
-                if (i + 1 < KM && i + 1 < k) v -= du[i] * x[i + 1];
-                if (i + 2 < KM && i + 2 < k) v -= du2[i] * x[i + 2];
-                x[i] = v / d[i];
-            }
-        }
-        double nrm = 0.0;
-#pragma unroll
-        for (int i = 0; i < KM; ++i) nrm += i < k ? x[i] * x[i] : 0.0;
-        nrm = sqrt(nrm);
-#pragma unroll
-        for (int i = 0; i < KM; ++i) x[i] = i < k ? (nrm > 0.0 ? x[i] / nrm : (i == 0 ? 1.0 : 0.0)) : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kMaxLanczos; ++i) scal->s[i] = i < KM ? x[i < KM ? i : 0] * (i < k ? 1.0 : 0.0) : 0.0;
+    ritz_largest<KM>(al, be, k, lo_hi, &scal->sigma, scal->s);
 }
 
 // q = V[:, 0..k) s (into u); pa <- ||q||^2
@@ -616,6 +494,7 @@ __global__ __launch_bounds__(256) void lz_q_kernel(const MatDesc *D, const WorkI
 __global__ void lz_qnorm_kernel(const MatDesc *D) {
     if (threadIdx.x != 0) return;
     const MatDesc &dm = D[blockIdx.x];
+    if (dm.fused) return;
     const double nrm = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
     dm.scal->qnorm_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
 }
@@ -641,6 +520,7 @@ __global__ __launch_bounds__(256) void lz_resid_kernel(const MatDesc *D, const W
 // matrix. A positive override replaces the bound (the norms are kept).
 __global__ __launch_bounds__(256) void lz_bound_kernel(const MatDesc *D, int force_fallback, double lam_override) {
     const MatDesc &dm = D[blockIdx.x];
+    if (dm.fused) return;
     Scalars *scal = dm.scal;
     const int64_t n = dm.n;
     __shared__ double sh_sum[256], sh_max[256];

@@ -85,7 +85,7 @@ struct MatDesc {
     double *V, *u, *w, *w2, *colsq, *pa, *pb, *sd, *sa, *sd2, *sa2;
     void *hi[4], *lo[4];  // work slots: X0, then rotating A / B / X_t
     int32_t nbv;          // vector blocks: ceil(n / 256)
-    int32_t pad_;
+    int32_t fused;        // 1: the whole projection runs in the one-workgroup small-matrix kernel
     double *U;            // deflation only: X v_j of every Lanczos step (n x steps), else null
     DeflState *defl;      // deflation only, else null
     int32_t cast_first;   // this matrix's run in the cast work list (adaptive-depth sums)

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -21,6 +22,7 @@
 #include "common.hpp"
 #include "gemm_sym.hpp"
 #include "runtime.hpp"
+#include "small_proj.hpp"
 
 // Workspace of psdproj_project_noalloc: one copy per device, held from the
 // library's load until the process ends. Host code must not use this name as
@@ -181,6 +183,19 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
 
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
+// Orders up to this value run the whole projection in the one-workgroup
+// small-matrix kernel (tuning key "small_max"; 0 = never).
+static std::atomic<int> g_small_max{kSmallEdge};
+
+// Whether matrix n of a plan runs in the one-workgroup kernel: half-precision
+// work formats with whole-stage splits, no adaptive depth, no deflation. The
+// rule depends only on (n, mode, options), so a matrix takes the same path
+// alone and in any batch.
+bool plan_fused(int64_t n, const StagePlan &p, int deflate, int small_max) {
+    const bool half = p.dtype == DT_F16 || p.dtype == DT_BF16 || p.dtype == DT_F16X8 || p.dtype == DT_BF16X8;
+    return n >= 1 && n <= small_max && half && !p.cubic && !p.adaptive && !p.b_only && deflate == 0 && p.T <= 16;
+}
+
 // Products of this matrix run on 256 tiles: plain ones whenever the size
 // calls for it, split ones where the split switch also allows it (FP32_EMU
 // has no plain products: every stage and the final product are split).
@@ -241,6 +256,7 @@ struct Plan {
     int64_t defl_ld = 0;   // caller's leading dimension when deflating
     uint32_t split_mask = 0;
     bool b_only = false;
+    int small_max = 0;     // the small-matrix rule the plan was laid out for
     std::vector<int64_t> ns;
     // layout
     StagePlan sp;
@@ -251,6 +267,10 @@ struct Plan {
     size_t off_desc = 0, off_io = 0, off_wvec = 0, off_wsymv = 0, off_wcast = 0, off_wgemm[3] = {0, 0, 0}, total = 0;
     size_t off_split = 0, off_fixup = 0, off_part = 0, off_adapt = 0;
     int64_t n_vec = 0, n_symv = 0, n_cast = 0, n_gemm[3] = {0, 0, 0}, n_split = 0, n_fixup = 0;
+    // matrices of the one-workgroup kernel (their list) and of the launch sequence
+    size_t off_wfused = 0;
+    int64_t n_fused = 0, n_seq = 0;
+    std::vector<bool> fused;
     int gemm_bm[3] = {256, 128, 128};
     TileLists tiles;
     int cus = 256;       // compute units the tail split is sized for
@@ -287,7 +307,7 @@ struct Plan {
                   int64_t dld) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
                ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld &&
-               stages == rq.T && adaptive == rq.adaptive && b_only == rq.b_only;
+               stages == rq.T && adaptive == rq.adaptive && b_only == rq.b_only && small_max == g_small_max.load();
     }
 };
 
@@ -296,12 +316,24 @@ void layout_plan(Plan &P) {
     P.mats.clear();
     P.mat_off.clear();
     P.n_vec = P.n_symv = P.n_cast = 0;
+    P.n_fused = P.n_seq = 0;
+    P.fused.clear();
     std::vector<int64_t> nps;
     std::vector<bool> big;
     std::vector<int> ksplit;
     for (int64_t n : P.ns) {
         P.mats.push_back(mat_layout(n, P.sp, P.steps, P.deflate > 0 ? P.defl_ld : 0));
         const MatLayout &L = P.mats.back();
+        const bool f = plan_fused(n, P.sp, P.deflate, P.small_max);
+        P.fused.push_back(f);
+        if (f) {  // no work items of the sequence: no tiles, no vector blocks
+            ++P.n_fused;
+            nps.push_back(0);
+            big.push_back(false);
+            ksplit.push_back(0);
+            continue;
+        }
+        ++P.n_seq;
         P.n_vec += vec_block_count(n);
         P.n_symv += symv_tile_count(n);
         P.n_cast += cast_tile_count(L.np);
@@ -322,6 +354,7 @@ void layout_plan(Plan &P) {
     P.off_wvec = take(sizeof(WorkItem) * (size_t)P.n_vec);
     P.off_wsymv = take(sizeof(WorkItem) * (size_t)P.n_symv);
     P.off_wcast = take(sizeof(WorkItem) * (size_t)P.n_cast);
+    P.off_wfused = take(sizeof(WorkItem) * (size_t)P.n_fused);
     for (int c = 0; c < 3; ++c) P.off_wgemm[c] = take(sizeof(WorkItem) * (size_t)P.n_gemm[c]);
     P.off_split = take(sizeof(uint4) * (size_t)P.n_split);
     P.off_fixup = take(sizeof(uint4) * (size_t)P.n_fixup);
@@ -339,7 +372,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     for (Plan::IoSlot &r : P.io_ring) r.valid = r.pinned = false;
     uint8_t *b = (uint8_t *)base;
     std::vector<MatDesc> desc(M);
-    std::vector<WorkItem> wv, wt, wc;
+    std::vector<WorkItem> wv, wt, wc, wf;
     std::vector<std::pair<DeflState *, DeflState>> defl_init;
     const bool split = P.sp.split_mask != 0 || P.sp.split_final;
     for (size_t m = 0; m < M; ++m) {
@@ -369,6 +402,11 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
             ds.ldd = P.defl_ld;
             defl_init.push_back(std::make_pair(d.defl, ds));
         }
+        if (P.fused[m]) {
+            d.fused = 1;
+            wf.push_back(WorkItem{(uint32_t)m, 0u});
+            continue;
+        }
         for (int64_t i = 0; i < vec_block_count(L.n); ++i) wv.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         for (int64_t i = 0; i < symv_tile_count(L.n); ++i) wt.push_back(WorkItem{(uint32_t)m, (uint32_t)i});
         d.cast_first = (int32_t)wc.size();
@@ -383,6 +421,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     if (!up(P.off_desc, desc.data(), sizeof(MatDesc) * M) || !up(P.off_wvec, wv.data(), sizeof(WorkItem) * wv.size()) ||
         !up(P.off_wsymv, wt.data(), sizeof(WorkItem) * wt.size()) ||
         !up(P.off_wcast, wc.data(), sizeof(WorkItem) * wc.size()) ||
+        !up(P.off_wfused, wf.data(), sizeof(WorkItem) * wf.size()) ||
         !up(P.off_wgemm[0], wg[0]->data(), sizeof(WorkItem) * wg[0]->size()) ||
         !up(P.off_wgemm[1], wg[1]->data(), sizeof(WorkItem) * wg[1]->size()) ||
         !up(P.off_wgemm[2], wg[2]->data(), sizeof(WorkItem) * wg[2]->size()) ||
@@ -475,6 +514,42 @@ int gemm_class(bool split_operands, int epi) {
     return (split_operands ? PSDPROJ_GEMM_PAIR : PSDPROJ_GEMM_PLAIN) + (epi == EPI_STORE_SPLIT ? 1 : 0);
 }
 
+bool stream_capturing(hipStream_t s);
+
+// Side stream of a (device, stream) on which the one-workgroup kernel of a
+// plan's small matrices overlaps the launch sequence of its other matrices,
+// with the events that fork it from the caller's stream and join it back.
+// Created outside stream capture only (a capture that finds none runs the
+// kernel on the caller's stream: same results, no overlap). Guarded by g_mu.
+struct Fork {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::map<std::pair<int, hipStream_t>, Fork> g_fork;
+
+Fork *get_fork(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = g_fork.find({dev, s});
+    if (it != g_fork.end()) return &it->second;
+    if (stream_capturing(s)) return nullptr;
+    Fork f;
+    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (f.fork) (void)hipEventDestroy(f.fork);
+        (void)hipStreamDestroy(f.side);
+        return nullptr;
+    }
+    return &(g_fork[{dev, s}] = f);
+}
+
+int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s, bool bound_only);
+
 // Enqueue the whole sequence for the plan's matrices. ios: host array of the
 // caller's I/O, one per matrix.
 int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bool want_info, bool bound_only) {
@@ -545,6 +620,59 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         if (capturing) r.pinned = true;
         B.io_tab = (const IoArg *)(b + P.off_io) + (size_t)hit * M;
     }
+    const StagePlan &p = P.sp;
+    Fork *fk = nullptr;
+    if (P.n_fused > 0) {
+        // every small matrix, whole, in one launch (one workgroup each)
+        SmallArgs a{};
+        a.D = B.desc;
+        a.list = (const WorkItem *)(b + P.off_wfused);
+        a.io_tab = B.io_tab;
+        a.io0 = B.io0;
+        a.T = p.T;
+        a.steps = P.steps;
+        a.split_mask = p.split_mask;
+        a.split_final = p.split_final ? 1 : 0;
+        a.bound_only = bound_only ? 1 : 0;
+        a.force_fallback = o.force_bound_fallback;
+        a.lam_override = o.lambda_override;
+        a.seed = kLanczosSeed;
+        for (int t = 0; t < p.T; ++t) {
+            a.a[t] = (float)p.a[t];
+            a.b[t] = (float)p.b[t];
+            a.c[t] = (float)p.c[t];
+            a.ea[t] = p.ea[t];
+            a.eb[t] = p.eb[t];
+        }
+        for (int t = 0; t <= p.T; ++t) a.ex[t] = p.ex[t];
+        // beside the launch sequence of the other matrices, on the side stream
+        hipStream_t ks = s;
+        if (P.n_seq > 0 && (fk = get_fork(s)) != nullptr) {
+            if (hipEventRecord(fk->fork, s) != hipSuccess || hipStreamWaitEvent(fk->side, fk->fork, 0) != hipSuccess)
+                return PSDPROJ_ERR_HIP;
+            ks = fk->side;
+        }
+        const hipError_t le = small_proj_launch(a, p.dtype, (int)P.n_fused, ks);
+        if (fk && hipEventRecord(fk->join, fk->side) != hipSuccess) return PSDPROJ_ERR_HIP;
+        if (le != hipSuccess) {
+            if (fk) (void)hipStreamWaitEvent(s, fk->join, 0);
+            return PSDPROJ_ERR_HIP;
+        }
+    }
+    const int st = P.n_seq > 0 ? run_sequence_of(P, B, o, s, bound_only) : PSDPROJ_OK;
+    // join the side stream whatever the sequence returned
+    if (fk && hipStreamWaitEvent(s, fk->join, 0) != hipSuccess) return PSDPROJ_ERR_HIP;
+    if (st != PSDPROJ_OK) return st;
+    if (want_info)
+        hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, bound_only ? 0 : p.T,
+                           (!bound_only && p.adaptive) ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
+}
+
+// The launch sequence of a plan's matrices other than the small ones.
+int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s, bool bound_only) {
+    uint8_t *b = (uint8_t *)P.base;
+    const StagePlan &p = P.sp;
     DeflLaunch DL;
     if (P.deflate > 0 && !bound_only) {
         // deflation (single projections): Lanczos on X recording X V, the
@@ -562,11 +690,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     }
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (bound_only) {
-        if (want_info) hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, 0, 0);
-        return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
-    }
-    const StagePlan &p = P.sp;
+    if (bound_only) return PSDPROJ_OK;
     const bool x0_split = p.split_final || ((p.split_mask & 1u) && !p.b_only);
     e = cast_x0(B, p.dtype, x0_split, p.ex[0], s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
@@ -683,9 +807,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
     g.adaptive = 0;
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (P.deflate > 0 && deflate_addback(DL, s) != hipSuccess) return PSDPROJ_ERR_HIP;
-    if (want_info)
-        hipLaunchKernelGGL(info_kernel, dim3(M), dim3(64), 0, s, B.desc, B.io_tab, B.io0, p.T, p.adaptive ? 1 : 0);
-    return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
+    return PSDPROJ_OK;
 }
 
 // Plan lookup/creation for (device, stream); builds tables when the shape or
@@ -712,6 +834,7 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     P->split_mask = sp.split_mask;
     P->split_final = sp.split_final;
     P->b_only = sp.b_only;
+    P->small_max = g_small_max.load();
     P->ns = ns;
     P->tile_gen = gemm_tile_generation();
     P->split_big = gemm_split_big(sp.dtype);
@@ -1029,6 +1152,12 @@ int psdproj_release(void) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     }
     g_pool.clear();
+    for (auto &kv : g_fork) {
+        (void)hipEventDestroy(kv.second.fork);
+        (void)hipEventDestroy(kv.second.join);
+        (void)hipStreamDestroy(kv.second.side);
+    }
+    g_fork.clear();
     for (auto &r : g_timer.pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1089,6 +1218,11 @@ int psdproj_tune(const char *key, int64_t value) {
         g_ld_pad = value;
         for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
         for (auto &kv : g_scratch) kv.second.plan.reset();
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "small_max")) {  // largest order of the one-workgroup kernel (0: never)
+        if (value < 0 || value > kSmallEdge) return PSDPROJ_ERR_INVALID_ARG;
+        g_small_max = (int)value;
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "class_choices_clear")) {  // drop the autotuner's per-size-class choices

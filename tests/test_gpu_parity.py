@@ -468,7 +468,9 @@ def test_deflation_refused_in_batches_and_bounded():
         P.project_ex(X, mode="fp16", deflate=9)
     assert e.value.status == 1
     # a spectrum without dominant pairs: nothing converges, nothing is removed,
-    # and the result is bitwise the undeflated one
+    # and the result is bitwise the undeflated one (an order above the
+    # one-workgroup kernel's, so both calls take the launch sequence)
+    X = to_dev(inputs.goe(200, 1))
     out, info_t = P.project_ex(X, mode="fp16", deflate=3)
     ref, _ = P.project_ex(X, mode="fp16")
     torch.cuda.synchronize()
