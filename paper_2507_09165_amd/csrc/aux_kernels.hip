@@ -139,7 +139,8 @@ enum SymvDst { DST_U = 0, DST_W = 1, DST_W2 = 2 };
 // arithmetic, so a workgroup keeps the whole 64 KB tile in flight. A
 // half-wave covers one 512-byte column segment per load. Row sums reduce the
 // 8 column groups through LDS; column dots reduce the 32 row quads through
-// LDS, both in a fixed order.
+// LDS, both in a fixed order (NORMS: the squares go through the same LDS
+// after the values, so the kernel keeps three workgroups per CU).
 template <bool NORMS>
 __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const WorkItem *W, const IoArg *io_tab,
                                                         IoArg io0, int src, int jstep, int stop_on_flag) {
@@ -159,8 +160,8 @@ __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const 
     const double *v = src == SRC_V ? dm.V + (int64_t)jstep * n : (src == SRC_W ? dm.w : dm.u);
     const double sc = src == SRC_QHAT ? dm.scal->qnorm_inv : 1.0;
     __shared__ double vI[kTB], vJ[kTB];
-    __shared__ double cpart[NORMS ? 2 : 1][kTB][NQ + 1];  // column dots per row quad (padded)
-    __shared__ double rpart[NORMS ? 2 : 1][NG][kTB];      // row sums per column group
+    __shared__ double cpart[kTB][NQ + 1];  // column dots per row quad (padded)
+    __shared__ double rpart[NG][kTB];      // row sums per column group
     const int tid = threadIdx.x;
     const int q = tid % NQ, grp = tid / NQ;  // row quad, column group
     const int64_t ir = i0 + 4 * q;           // first row of the quad
@@ -194,12 +195,13 @@ __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const 
 #pragma unroll
     for (int e = 0; e < 4; ++e) va[e] = vI[4 * q + e];
     double ra[4] = {0.0, 0.0, 0.0, 0.0}, rq[4] = {0.0, 0.0, 0.0, 0.0};
+    double sq[NORMS ? NL : 1];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int c = grp + NG * k;
         const int64_t j = j0 + c;
         const double vj = vJ[c];
-        double dot = 0.0, sq = 0.0;
+        double dot = 0.0, sqk = 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const double xe = (double)x[k][e];
@@ -208,38 +210,41 @@ __global__ __launch_bounds__(256) void symv_tile_kernel(const MatDesc *D, const 
             const bool up = !diag || ir + e < j;
             ra[e] += up ? xe * vj : 0.0;
             if constexpr (NORMS) {
-                sq += xe * xe;
+                sqk += xe * xe;
                 rq[e] += up ? xe * xe : 0.0;
             }
         }
-        cpart[0][c][q] = dot;
-        if constexpr (NORMS) cpart[NORMS ? 1 : 0][c][q] = sq;
+        cpart[c][q] = dot;
+        if constexpr (NORMS) sq[k] = sqk;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        rpart[0][grp][4 * q + e] = ra[e];
-        if constexpr (NORMS) rpart[NORMS ? 1 : 0][grp][4 * q + e] = rq[e];
-    }
+    for (int e = 0; e < 4; ++e) rpart[grp][4 * q + e] = ra[e];
     __syncthreads();
     const int64_t base = (int64_t)t * kTB;
-    if (tid < kTB) {
-        double d = 0.0, d2 = 0.0;
-        for (int k = 0; k < NQ; ++k) {
-            d += cpart[0][tid][k];
-            if constexpr (NORMS) d2 += cpart[NORMS ? 1 : 0][tid][k];
-        }
-        dm.sd[base + tid] = d;
-        if constexpr (NORMS) dm.sd2[base + tid] = d2;
-    } else {
-        const int r = tid - kTB;
-        double a = 0.0, a2 = 0.0;
+    // column sums of the row-quad partials (threads 0..127) and row sums of
+    // the column-group partials (threads 128..255), in a fixed order
+    auto reduce_out = [&](double *dcol, double *arow) {
+        if (tid < kTB) {
+            double d = 0.0;
+            for (int k = 0; k < NQ; ++k) d += cpart[tid][k];
+            dcol[base + tid] = d;
+        } else {
+            const int r = tid - kTB;
+            double a = 0.0;
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            a += rpart[0][g][r];
-            if constexpr (NORMS) a2 += rpart[NORMS ? 1 : 0][g][r];
+            for (int g = 0; g < NG; ++g) a += rpart[g][r];
+            arow[base + r] = a;
         }
-        dm.sa[base + r] = a;
-        if constexpr (NORMS) dm.sa2[base + r] = a2;
+    };
+    reduce_out(dm.sd, dm.sa);
+    if constexpr (NORMS) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NL; ++k) cpart[grp + NG * k][q] = sq[k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rpart[grp][4 * q + e] = rq[e];
+        __syncthreads();
+        reduce_out(dm.sd2, dm.sa2);
     }
 }
 
