@@ -220,29 +220,42 @@ def batched_leg(steps=3, warmup=1, count=256, mode="fp8_bf16_split"):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    # the same call captured once in a HIP graph and replayed
+    # the same call captured once in a HIP graph and replayed; every replay's
+    # outputs are checked bitwise against the eager call's
+    ref = [o.clone() for o in outs]
     gs = torch.cuda.Stream()
     P.project_batched(Xs, outs, mode=mode, stream=gs)
     gs.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=gs):
         P.project_batched(Xs, outs, mode=mode, stream=gs)
+    for o in outs:
+        o.fill_(float("nan"))
+    torch.cuda.synchronize()
     graph.replay()
     torch.cuda.synchronize()
+    replay_equal = all(torch.equal(o, r) for o, r in zip(outs, ref))
+    # replays timed by the host clock around a device synchronisation (events
+    # recorded on the launch stream have bracketed less than the replayed
+    # graph's work when it forks to other streams); the event time beside it
+    t0 = time.perf_counter()
     ev0.record(gs)
     for _ in range(steps):
         with torch.cuda.stream(gs):
             graph.replay()
     ev1.record(gs)
     torch.cuda.synchronize()
-    gms = ev0.elapsed_time(ev1) / steps
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    gms_ev = ev0.elapsed_time(ev1) / steps
+    replay_equal = replay_equal and all(torch.equal(o, r) for o, r in zip(outs, ref))
     del graph
     flops = sum(P.gemm_count(mode) * float(n) * n * (n + 1) for n in sizes)
     return {"workload": f"{count} GOE blocks, n log-uniform in [32, 1024] (seed 7), {mode}",
             "ms_per_batch": ms, "host_ms_per_batch": wall, "proj_per_s": count / (ms * 1e-3),
             "algorithmic_tflops": flops / (ms * 1e-3) / 1e12, "n_min": int(sizes.min()),
             "n_max": int(sizes.max()), "steps": steps,
-            "graph": {"ms_per_batch": gms, "proj_per_s": count / (gms * 1e-3)}}
+            "graph": {"ms_per_batch": gms, "proj_per_s": count / (gms * 1e-3), "event_ms_per_batch": gms_ev,
+                      "outputs_equal_eager": replay_equal}}
 
 
 def serving_leg(num=2000, rho=(0.5, 0.8, 0.95), slots=4, seed=11, sat_num=400):

@@ -199,15 +199,15 @@ int psdproj_spectral_bound(int64_t n, int64_t ld, const float *X, int lanczos_st
  * leading dimensions and device pointers). Matrices are independent; each
  * result equals the one psdproj_project gives for that matrix alone.
  *
- * Small matrices: in the half-precision modes (FP16, BF16, FP16_SPLIT,
- * FP8_FP16_SPLIT, FP8_BF16_SPLIT) without deflation, adaptive depth or
- * split_mask's B-only flag, a matrix of order n <= 128 (tuning key
- * "small_max") runs all of Algorithm 2 in one workgroup: every such matrix of
- * a call in one launch, which a batched call runs on a side stream of the
- * caller's stream beside the launch sequence of its larger matrices (forked
- * and joined by events; under capture before the side stream exists, on the
- * caller's stream). The rule depends only on (n, mode, options), so a matrix
- * takes the same path alone and in any batch.
+ * Small matrices: in the modes whose work matrices are FP16 or BF16 (FP16,
+ * BF16, FP16_SPLIT, FP8_FP16_SPLIT, FP8_BF16_SPLIT, FP32_EMU) without
+ * deflation, adaptive depth or split_mask's B-only flag, a matrix of order
+ * n <= 128 (tuning key "small_max") runs all of Algorithm 2 in one
+ * workgroup: every such matrix of a call in one launch, which a batched call
+ * runs on a side stream of the caller's stream beside the launch sequence of
+ * its larger matrices (forked and joined by events; under capture before the
+ * side stream exists, on the caller's stream). The rule depends only on
+ * (n, mode, options), so a matrix takes the same path alone and in any batch.
  *
  * Graph capture (this call and psdproj_project / _ex / _batched_ex): a call
  * with the sizes, mode and options of the previous call on the same stream

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <memory>
@@ -550,6 +551,48 @@ Fork *get_fork(hipStream_t s) {
 
 int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s, bool bound_only);
 
+// Side streams on which the groups of a batched call run beside the caller's
+// stream (tuning key "batch_streams": groups per batched call, 1..4; default
+// 2), with the event that forks them and one join event each. Created
+// outside stream capture only (a capture that finds too few runs the batch
+// as one group). Guarded by g_mu.
+static std::atomic<int> g_batch_streams{2};
+struct BatchFork {
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+};
+std::map<std::pair<int, hipStream_t>, BatchFork> g_bfork;
+
+BatchFork *get_bfork(hipStream_t s, int nside, bool capturing) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    BatchFork &bf = g_bfork[{dev, s}];
+    if ((int)bf.side.size() >= nside) return &bf;
+    if (capturing) return nullptr;
+    if (!bf.fork && hipEventCreateWithFlags(&bf.fork, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        bf.fork = nullptr;
+        return nullptr;
+    }
+    while ((int)bf.side.size() < nside) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamDestroy(st);
+            return nullptr;
+        }
+        bf.side.push_back(st);
+        bf.join.push_back(ev);
+    }
+    return &bf;
+}
+
 // Enqueue the whole sequence for the plan's matrices. ios: host array of the
 // caller's I/O, one per matrix.
 int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bool want_info, bool bound_only) {
@@ -845,15 +888,17 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     return P;
 }
 
+// capture_hint: treat s as capturing (a side stream that a captured call is
+// about to fork is not capturing yet).
 int prepare(const psdproj_opts &o, int steps, const std::vector<int64_t> &ns, int64_t defl_ld, hipStream_t s,
-            Plan **out) {
+            Plan **out, bool capture_hint = false) {
     load_env_tune_cache();
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_ERR_HIP;
     StagePlan sp;
     if (!make_stage_plan(o, sp)) return PSDPROJ_ERR_INVALID_ARG;
     Pool &pool = g_pool[{dev, s}];
-    auto capturing = [&]() { return stream_capturing(s); };
+    auto capturing = [&]() { return capture_hint || stream_capturing(s); };
     if (!pool.plan || !pool.plan->same_key(o, sp, steps, ns, defl_ld)) {
         if (capturing()) return PSDPROJ_ERR_UNSUPPORTED;
         std::unique_ptr<Plan> P = new_plan(o, sp, steps, ns, defl_ld, dev);
@@ -981,6 +1026,70 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
     if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
+    // Groups on concurrent streams: the launch sequence of a batch is bound
+    // by latency (every launch waits for the previous one, and most leave CUs
+    // idle), so two groups' sequences overlap. The matrices of the
+    // one-workgroup kernel stay in group 0, on the caller's stream (its own
+    // fork then comes from the caller's stream; a side stream never forks
+    // again); the others are dealt out largest first (cost n^3) to the group
+    // with the least cost so far.
+    int G = std::min<int>(g_batch_streams.load(), (int)ns.size());
+    std::vector<std::vector<int>> grp(G > 1 ? G : 1);
+    if (G > 1) {
+        std::vector<int> order;
+        for (size_t i = 0; i < ns.size(); ++i) {
+            if (plan_fused(ns[i], tmp, o.deflate, g_small_max.load())) grp[0].push_back((int)i);
+            else order.push_back((int)i);
+        }
+        auto cost = [&](int i) { const double m = (double)ns[i]; return m * m * m; };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        std::vector<double> load(G, 0.0);
+        for (int i : order) {
+            const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            grp[g].push_back(i);
+            load[g] += cost(i);
+        }
+        // drop empty groups (group 0 may be empty only if every matrix is large)
+        std::vector<std::vector<int>> keep;
+        for (int g = 0; g < G; ++g)
+            if (!grp[g].empty() || g == 0) keep.push_back(grp[g]);
+        if (keep[0].empty()) keep.erase(keep.begin());
+        grp.swap(keep);
+        G = (int)grp.size();
+    }
+    if (G > 1) {
+        for (auto &v : grp) std::sort(v.begin(), v.end());  // each group in the caller's order
+        const bool cap = stream_capturing(s);
+        BatchFork *bf = get_bfork(s, G - 1, cap);
+        if (bf) {
+            std::vector<Plan *> plans(G, nullptr);
+            std::vector<std::vector<IoArg>> gio(G);
+            auto stream_of = [&](int g) { return g == 0 ? s : bf->side[g - 1]; };
+            for (int g = 0; g < G; ++g) {
+                std::vector<int64_t> gn;
+                for (int i : grp[g]) {
+                    gn.push_back(ns[i]);
+                    gio[g].push_back(ios[i]);
+                }
+                const int st = prepare(o, steps, gn, 0, stream_of(g), &plans[g], cap);
+                if (st != PSDPROJ_OK) return st;
+            }
+            if (hipEventRecord(bf->fork, s) != hipSuccess) return PSDPROJ_ERR_HIP;
+            for (int g = 1; g < G; ++g)
+                if (hipStreamWaitEvent(stream_of(g), bf->fork, 0) != hipSuccess) return PSDPROJ_ERR_HIP;
+            int st = PSDPROJ_OK;
+            for (int g = 0; g < G; ++g) {
+                const int sg = run_plan(*plans[g], gio[g].data(), o, stream_of(g), info != nullptr, false);
+                if (st == PSDPROJ_OK) st = sg;
+            }
+            // join every side stream whatever the groups returned
+            for (int g = 1; g < G; ++g)
+                if (hipEventRecord(bf->join[g - 1], stream_of(g)) != hipSuccess ||
+                    hipStreamWaitEvent(s, bf->join[g - 1], 0) != hipSuccess)
+                    st = PSDPROJ_ERR_HIP;
+            return st;
+        }
+    }
     Plan *P = nullptr;
     const int st = prepare(o, steps, ns, 0, s, &P);
     if (st != PSDPROJ_OK) return st;
@@ -1018,24 +1127,40 @@ size_t workspace_bytes_batch(const int64_t *ns, int count, int mode) {
 
 size_t workspace_bytes_for(int64_t n, int mode) { return workspace_bytes_batch(&n, 1, mode); }
 
+// The workspace a stream's calls hold: its own pool and those of the side
+// streams its batched calls run groups on.
 size_t pool_held(hipStream_t s) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_pool.find({dev, s});
-    return it == g_pool.end() ? 0 : it->second.bytes;
+    size_t held = 0;
+    auto add = [&](hipStream_t st) {
+        auto it = g_pool.find({dev, st});
+        if (it != g_pool.end()) held += it->second.bytes;
+    };
+    add(s);
+    auto bf = g_bfork.find({dev, s});
+    if (bf != g_bfork.end())
+        for (hipStream_t st : bf->second.side) add(st);
+    return held;
 }
 
 void pool_release(hipStream_t s) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_pool.find({dev, s});
-    if (it == g_pool.end()) return;
-    (void)hipStreamSynchronize(s);
-    it->second.plan.reset();
-    if (it->second.ptr) (void)hipFree(it->second.ptr);
-    g_pool.erase(it);
+    auto drop = [&](hipStream_t st) {
+        auto it = g_pool.find({dev, st});
+        if (it == g_pool.end()) return;
+        (void)hipStreamSynchronize(st);
+        it->second.plan.reset();
+        if (it->second.ptr) (void)hipFree(it->second.ptr);
+        g_pool.erase(it);
+    };
+    auto bf = g_bfork.find({dev, s});
+    if (bf != g_bfork.end())
+        for (hipStream_t st : bf->second.side) drop(st);
+    drop(s);
 }
 
 double gemm_count_for(const psdproj_opts &o) {
@@ -1158,6 +1283,12 @@ int psdproj_release(void) {
         (void)hipStreamDestroy(kv.second.side);
     }
     g_fork.clear();
+    for (auto &kv : g_bfork) {
+        if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
+        for (hipEvent_t e : kv.second.join) (void)hipEventDestroy(e);
+        for (hipStream_t st : kv.second.side) (void)hipStreamDestroy(st);  // their pools and forks went above
+    }
+    g_bfork.clear();
     for (auto &r : g_timer.pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1218,6 +1349,11 @@ int psdproj_tune(const char *key, int64_t value) {
         g_ld_pad = value;
         for (auto &kv : g_pool) kv.second.plan.reset();  // layouts change: rebuild plans
         for (auto &kv : g_scratch) kv.second.plan.reset();
+        return PSDPROJ_OK;
+    }
+    if (!strcmp(key, "batch_streams")) {  // concurrent groups of a batched call (1..4)
+        if (value < 1 || value > 4) return PSDPROJ_ERR_INVALID_ARG;
+        g_batch_streams = (int)value;
         return PSDPROJ_OK;
     }
     if (!strcmp(key, "small_max")) {  // largest order of the one-workgroup kernel (0: never)

@@ -1,6 +1,6 @@
-"""The one-workgroup path of small matrices (n <= 128 in the half-precision
-modes): the whole of Algorithm 2 for one matrix in one workgroup, one launch
-for every small matrix of a call.
+"""The one-workgroup path of small matrices (n <= 128 in the FP16/BF16 work
+formats, FP32_EMU included): the whole of Algorithm 2 for one matrix in one
+workgroup, one launch for every small matrix of a call.
 
 Against the oracle: the spectral bound (Theorem 2) to 1e-9 and the FP64
 composite polynomial with the device's bound, entry by entry and in relative
@@ -21,7 +21,8 @@ from gpu_util import dev, rel_fro, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp8_bf16_split"]
+MODES = ["fp16", "bf16", "fp16_split", "fp8_fp16_split", "fp8_bf16_split", "fp32_emu"]
+TOL = {"fp32_emu": 1e-5}
 TOL_POLY = 5e-3
 SIZES = [1, 2, 3, 15, 16, 17, 31, 32, 33, 48, 63, 64, 65, 97, 100, 127, 128]
 
@@ -62,12 +63,12 @@ def test_small_against_oracle(mode):
             # is measured against the bound, the scale of every eigenvalue
             e = float(np.linalg.norm(out - ref)) / info["lambda"]
             say(f"  n={n}: vs oracle {e:.3e} of lam")
-            assert e <= TOL_POLY, (n, e)
+            assert e <= TOL.get(mode, TOL_POLY), (n, e)
             continue
         e = rel_fro(out, ref)
         say(f"  n={n}: vs oracle {e:.3e}, max abs {emax:.3e}")
-        assert e <= TOL_POLY, (n, e)
-        assert emax <= _max_abs_bound(ref, TOL_POLY), (n, emax)
+        assert e <= TOL.get(mode, TOL_POLY), (n, e)
+        assert emax <= _max_abs_bound(ref, TOL.get(mode, TOL_POLY)), (n, emax)
 
 
 @pytest.mark.parametrize("mode", ["fp16", "fp8_bf16_split"])
@@ -163,3 +164,43 @@ def test_small_split_ablation():
     say("  n=128 fp8_bf16_split plain vs default", errs)
     assert errs["default"] <= TOL_POLY
     assert errs["default"] < errs["plain"]
+
+
+@pytest.mark.parametrize("mode", ["fp8_bf16_split", "fp16"])
+def test_batch_groups_on_streams_equal_single(mode):
+    """A batched call runs its matrices as size-balanced groups on concurrent
+    streams (batch_streams = 1..4): every result is bitwise the single call's,
+    also through a captured graph replayed with eager work in between."""
+    import torch
+    sizes = [1000, 33, 600, 128, 257, 700, 90, 400, 5, 850]
+    Xs = [to_dev(_matrix(n, 600 + n)) for n in sizes]
+    alone = [P.project(X, mode=mode) for X in Xs]
+    torch.cuda.synchronize()
+    try:
+        for g in (1, 2, 3, 4):
+            P.tune("batch_streams", g)
+            outs = P.project_batched(Xs, mode=mode)
+            torch.cuda.synchronize()
+            for o, a, n in zip(outs, alone, sizes):
+                assert torch.equal(o, a), (g, n)
+        P.tune("batch_streams", 2)
+        s = torch.cuda.Stream()
+        outs = [torch.empty_like(X) for X in Xs]
+        P.project_batched(Xs, outs, mode=mode, stream=s)
+        s.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            P.project_batched(Xs, outs, mode=mode, stream=s)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1.0)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            for o, a, n in zip(outs, alone, sizes):
+                assert torch.equal(o, a), (rep, n)
+            P.project(Xs[0], mode="fp16")  # eager work between replays
+            torch.cuda.synchronize()
+        del graph
+    finally:
+        P.tune("batch_streams", 2)

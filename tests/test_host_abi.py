@@ -111,16 +111,17 @@ def test_tuning_keys_validate_their_values():
     assert t("no_such_key", 1) != 0
     for key, bad in (("gemm_tile", 64), ("gemm_big_min", -1), ("gemm_tail_cus", -1), ("gemm_split_big", 4),
                      ("gemm_ksplit", 0), ("gemm_block", 0), ("work_ld_pad", 100), ("work_ld_pad", -64),
-                     ("small_max", -1), ("small_max", 129)):
+                     ("small_max", -1), ("small_max", 129), ("batch_streams", 0), ("batch_streams", 5)):
         assert t(key, bad) == 1, (key, bad)
     try:
         for key, ok in (("gemm_tile", 256), ("gemm_tile", 128), ("gemm_big_min", 512), ("gemm_tail_cus", 64),
                         ("gemm_split_big", 0), ("gemm_ksplit", 1), ("gemm_block", (4 << 8) | 4),
-                        ("small_max", 0), ("small_max", 64)):
+                        ("small_max", 0), ("small_max", 64), ("batch_streams", 1), ("batch_streams", 4)):
             assert t(key, ok) == 0, (key, ok)
     finally:
         for key, v in (("gemm_tile", 0), ("gemm_big_min", 0), ("gemm_tail_cus", 0), ("gemm_split_big", 3),
-                       ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4), ("small_max", 128)):
+                       ("gemm_ksplit", 8), ("gemm_block", (4 << 8) | 4), ("small_max", 128),
+                       ("batch_streams", 2)):
             assert t(key, v) == 0
 
 
