@@ -127,6 +127,7 @@ int psdproj_admm_dual(int64_t n, int64_t ld, const float *X, const float *S, con
     if (!X || !S || !C || !b || !y || !W) return PSDPROJ_ERR_INVALID_ARG;
     if (n > 65535) return PSDPROJ_ERR_UNSUPPORTED;  // one grid row per column
     const dim3 grid((unsigned)((n + kAdmmThreads - 1) / kAdmmThreads), (unsigned)n);
+    (void)hipGetLastError();  // a pending error of an earlier runtime call is not this call's
     hipLaunchKernelGGL(admm_dual_kernel, grid, dim3(kAdmmThreads), 0, (hipStream_t)stream, n, ld, X, S, C, b,
                        1.0 / sigma, y, W);
     return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
@@ -140,6 +141,7 @@ int psdproj_admm_primal(int64_t n, int64_t ld, float *X, const float *S, const f
     const int groups = (int)(n < kAdmmGroups ? n : kAdmmGroups);
     double *part = res + 8;
     hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();  // a pending error of an earlier runtime call is not this call's
     hipLaunchKernelGGL(admm_primal_kernel, dim3((unsigned)groups), dim3(kAdmmThreads), 0, s, n, ld, X, S, C, y, b,
                        sigma, part);
     hipLaunchKernelGGL(admm_residual_kernel, dim3(1), dim3(kAdmmThreads), 0, s, n, y, b, part, groups, res);

@@ -980,8 +980,12 @@ int prepare_scratch(const psdproj_opts &o, int steps, int64_t n, int64_t defl_ld
 
 }  // namespace
 
+// Launch errors are read with hipGetLastError; a call first clears whatever
+// error an earlier runtime call of the thread (another library's included)
+// left pending, so a failure it reports is its own.
 int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X, float *out, hipStream_t s,
                    psdproj_info *info, bool bound_only, bool no_alloc) {
+    (void)hipGetLastError();
     StagePlan tmp;
     if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
@@ -1006,6 +1010,7 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
 
 int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_t *ld, const float *const *X,
                 float *const *out, hipStream_t s, psdproj_info *info) {
+    (void)hipGetLastError();  // see run_projection
     StagePlan tmp;
     if (!make_stage_plan(o, tmp)) return PSDPROJ_ERR_INVALID_ARG;
     if (count < 0 || (count > 0 && (!n || !ld || !X || !out))) return PSDPROJ_ERR_INVALID_ARG;
@@ -1464,6 +1469,7 @@ static int sym_gemm_impl(int dtype, int64_t n_p, int64_t ld, const void *L, cons
     g.sl = 0; g.sr = 1; g.sc0 = C0 ? 2 : -1; g.sd = 3; g.c0_split = C0lo ? 1 : 0;
     g.alpha = alpha; g.beta = beta; g.gamma = gamma;
     if (es) { g.es_l = es[0]; g.es_r = es[1]; g.es_c0 = es[2]; g.es_d = es[3]; }
+    (void)hipGetLastError();  // see run_projection
     const hipError_t e = gemm_sym_launch(g, dtype, Dlo ? EPI_STORE_SPLIT : EPI_STORE, Llo != nullptr, Rlo != nullptr,
                                          bm, (int64_t)tiles.size(), s);
     return e == hipSuccess ? PSDPROJ_OK : PSDPROJ_ERR_HIP;
