@@ -113,6 +113,16 @@ __device__ __forceinline__ int xcd_remap(int w, int count) {
 
 constexpr int kThreads = 256;  // 4 waves in a 2 x 2 layout
 
+// A pointer every lane of the wave holds, moved to scalar registers (the
+// compiler cannot always prove a value loaded through the descriptor table
+// uniform).
+__device__ __forceinline__ const uint8_t *wave_uniform(const uint8_t *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const uint8_t *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 typedef __attribute__((address_space(1))) void *gptr_t;
 typedef __attribute__((address_space(3))) void *lptr_t;
 
@@ -243,40 +253,61 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     constexpr int RPL = 1024 / ROWB;  // LDS rows per wave load
     static_assert(STAGE % 4096 == 0, "stage split over waves");
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-    const uint8_t *gsrc[NLD];
+    // Each load's address is a base shared by the wave (scalar registers,
+    // advanced per K-tile by scalar arithmetic) plus a fixed 32-bit per-lane
+    // offset, so the K loop spends no vector instructions on addresses. COMB
+    // rows take each lane's part from one of two buffers: 64-bit per-lane
+    // addresses there.
+    const uint8_t *gbase[NLD];
+    uint32_t goff[NLD];
+    const uint8_t *gsrc[COMB ? NLD : 1];
     int gstep[NLD];  // bytes a source row advances per K-tile
+    int gsh[NLD];    // its log2 (steps are powers of two)
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
-        const int kb = (wave * NLD + j) * 1024;  // byte offset in the stage
+        const int kb = (wave_u * NLD + j) * 1024;  // byte offset in the stage (uniform)
         gstep[j] = TB;
+        gsh[j] = __builtin_ctz(TB);
         if constexpr (PAIR8) {
             // panels: L hi, L codes, R hi[, R codes] (every 1-KB load lies in one)
             const int side = kb >= P8HI + P8LO ? 1 : 0;
             const int off = kb - side * (P8HI + P8LO);
             const bool is_hi = off < P8HI;
             const int w = is_hi ? 64 : 32, nch = w / 16;
-            const int r = (is_hi ? off : off - P8HI) / w + lane / nch;
+            const int rb = (is_hi ? off : off - P8HI) / w;  // first row of the load (uniform)
+            const int rl = lane / nch;                      // the lane's row in it
             const int pc = lane % nch;
-            const int c = is_hi ? swz<4>(r, pc) : swz<2>(r, pc);
-            const int64_t row = (side == 0 ? i0 : j0) + r;
+            const int c = is_hi ? swz<4>(rb + rl, pc) : swz<2>(rb + rl, pc);
+            const int64_t row0 = (side == 0 ? i0 : j0) + rb;  // a multiple of 4
             // hi: row-major 64-byte segments of the FP16 column; codes: the
             // tiled code buffer, 32 bytes of column `row` per 32-K block
-            gsrc[j] = is_hi ? src[2 * side] + row * ld * 2 + (c << 4)
-                            : src[2 * side + 1] + (row >> 2) * 4 * ld + 32 * (row & 3) + (c << 4);
+            if (is_hi) {
+                gbase[j] = wave_uniform(src[2 * side] + row0 * ld * 2);
+                goff[j] = (uint32_t)(rl * ld * 2 + (c << 4));
+            } else {
+                gbase[j] = wave_uniform(src[2 * side + 1] + (row0 >> 2) * 4 * ld);
+                goff[j] = (uint32_t)((rl >> 2) * 4 * ld + 32 * (rl & 3) + (c << 4));
+            }
             gstep[j] = is_hi ? 64 : 128;
+            gsh[j] = is_hi ? 6 : 7;
             continue;
         }
         const int p = kb / PANEL;
-        const int r = (kb % PANEL) / ROWB + lane / NCH;
+        const int rb = (kb % PANEL) / ROWB;
+        const int rl = lane / NCH;
+        const int r = rb + rl;
         const int pc = lane % NCH;
         const int c = swz<NCH>(r, pc);
         if constexpr (COMB) {
             // panel p is operand p; chunk c < HCH is hi, the rest lo / pair
             const int64_t row = (p == 0 ? i0 : j0) + r;
             gsrc[j] = src[2 * p + (c >= HCH ? 1 : 0)] + row * ld * (int64_t)sizeof(T) + ((c % HCH) << 4);
+            gbase[j] = nullptr;
+            goff[j] = 0;
         } else {
-            const int64_t row = (p < NLP ? i0 : j0) + r;
-            gsrc[j] = src[p] + row * ld * (int64_t)sizeof(T) + (c << 4);
+            const int64_t row0 = (p < NLP ? i0 : j0) + rb;
+            gbase[j] = wave_uniform(src[p] + row0 * ld * (int64_t)sizeof(T));
+            goff[j] = (uint32_t)(rl * ld * (int64_t)sizeof(T) + (c << 4));
         }
     }
     // The loads are written as inline asm (M0 = LDS destination, one s_nop
@@ -288,10 +319,17 @@ __global__ __launch_bounds__(kThreads) void gemm_sym_kernel(GemmArgs g) {
     // below), as before.
     auto issue_one = [&](int64_t kt, int buf, int j) {
         const uint32_t la = (uint32_t)(uintptr_t)(smem + buf * STAGE + (wave_u * NLD + j) * 1024);
-        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                     :
-                     : "v"(gsrc[j] + kt * gstep[j]), "s"(la)
-                     : "memory", "m0");
+        if constexpr (COMB) {
+            asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                         :
+                         : "v"(gsrc[j] + kt * gstep[j]), "s"(la)
+                         : "memory", "m0");
+        } else {
+            asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                         :
+                         : "v"(goff[j]), "s"(gbase[j] + (kt << gsh[j])), "s"(la)
+                         : "memory", "m0");
+        }
     };
     auto issue_loads = [&](int64_t kt, int buf) {
 #pragma unroll
