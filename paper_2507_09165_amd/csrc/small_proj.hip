@@ -307,7 +307,8 @@ __global__ __launch_bounds__(256) void small_proj_kernel(SmallArgs g) {
         sm_orth(V, hv, j, w);
         sm_dots(V, w, j, part, hv);          // second pass
         sm_orth(V, hv, j, w);
-        const double beta = sqrt(sum128(t < NE ? w[t < NE ? t : 0] * w[t < NE ? t : 0] : 0.0, red));
+        const double wt = t < NE ? w[t] : 0.0;
+        const double beta = sqrt(sum128(wt * wt, red));
         const bool stop = (j == g.steps - 1) || !(beta > 1e-13 * amax);
         if (t == 0) {
             al[j] = alpha;
