@@ -377,12 +377,18 @@ __global__ __launch_bounds__(256) void lz_start_kernel(const MatDesc *D, const W
 }
 
 // Orthogonalisation pass of step j over the rows of this block.
-//  pass 1: h = sum(pa); alpha_j = h_j; w -= V h; pb <- V^T w (second GS pass)
-//  pass 2: h = sum(pb); w -= V h; pa <- ||w||^2
+//  pass 1: h = sum(pa); alpha_j = h_j; w -= V h; pb <- V^T w (second GS
+//          pass), pc <- ||w||^2
+//  pass 2: h = sum(pb); w -= V h; beta_j = ||w|| as sqrt(sum(pc) - |h|^2)
+//          (w changes by V h with V orthonormal, so its squared norm drops by
+//          |h|^2; after the first pass h is at rounding level, so the two
+//          agree to rounding); stop if beta_j <= 1e-13 max|alpha| or j is the
+//          last step, else V[:, j+1] = w / beta_j
 // (the first pass's partials come with the reduction that formed w). Thread
 // group g holds the columns c = 4 m + g of V for its row: (V h)_i is the sum
 // of the four groups' sums, added in group order.
-__global__ __launch_bounds__(kVecThreads) void lz_orth_kernel(const MatDesc *D, const WorkItem *W, int j, int pass) {
+__global__ __launch_bounds__(kVecThreads) void lz_orth_kernel(const MatDesc *D, const WorkItem *W, int j, int pass,
+                                                              int steps) {
     const WorkItem wi = W[blockIdx.x];
     const MatDesc &dm = D[wi.x];
     Scalars *scal = dm.scal;
@@ -391,7 +397,6 @@ __global__ __launch_bounds__(kVecThreads) void lz_orth_kernel(const MatDesc *D, 
     const int r = threadIdx.x % kRows, g = threadIdx.x / kRows;
     const int64_t i = (int64_t)b * kRows + r, n = dm.n;
     const double *part_in = pass == 1 ? dm.pa : dm.pb;
-    double *part_out = pass == 1 ? dm.pb : dm.pa;
     __shared__ double hsh[kMaxLanczos];
     __shared__ double rs[kGroups][kRows];
     __shared__ double wb[kRows];
@@ -431,28 +436,22 @@ __global__ __launch_bounds__(kVecThreads) void lz_orth_kernel(const MatDesc *D, 
 #pragma unroll
         for (int m = 0; m < kColsPerGroup; ++m) h[m] = v[m] * wb[r];
         group_reduce<kColsPerGroup>(h, sh, hs);
-        if (threadIdx.x <= j) part_out[(int64_t)b * kMaxLanczos + threadIdx.x] = hs[threadIdx.x % kGroups][threadIdx.x / kGroups];
-    } else {
-        double x[1] = {wb[r] * wb[r]};
+        if (threadIdx.x <= j) dm.pb[(int64_t)b * kMaxLanczos + threadIdx.x] = hs[threadIdx.x % kGroups][threadIdx.x / kGroups];
+        double x[1] = {g == 0 ? wb[r] * wb[r] : 0.0};
         group_reduce<1>(x, sh, (double(*)[1])hs);
-        if (threadIdx.x == 0) part_out[(int64_t)b * kMaxLanczos] = hs[0][0];
+        if (threadIdx.x == 0) dm.pc[b] = hs[0][0];
+        return;
     }
-}
-
-// beta_j = ||w|| (from pa); stop if beta_j <= 1e-13 max|alpha| or j is the
-// last step, else V[:, j+1] = w / beta_j.
-__global__ __launch_bounds__(256) void lz_next_kernel(const MatDesc *D, const WorkItem *W, int j, int steps) {
-    const WorkItem wi = W[blockIdx.x];
-    const MatDesc &dm = D[wi.x];
-    Scalars *scal = dm.scal;
-    if (scal->stop) return;
-    const int b = (int)wi.y;
-    const int64_t i = (int64_t)b * kRows + threadIdx.x, n = dm.n;
-    const double beta = sqrt(sum_partials(dm.pa, dm.nbv, kMaxLanczos, 0));
+    // pass 2: beta_j from the norm and the second pass's coefficients, the
+    // same in every block (fixed-order sums of the same partials)
+    double hh = 0.0;
+    for (int c = 0; c <= j; ++c) hh += hsh[c] * hsh[c];
+    const double beta = sqrt(fmax(sum_partials(dm.pc, dm.nbv, 1, 0) - hh, 0.0));
     const bool stop = (j == steps - 1) || !(beta > 1e-13 * scal->amax);
-    if (!stop && i < n) dm.V[(int64_t)(j + 1) * n + i] = dm.w[i] / beta;
+    if (g == 0 && !stop && i < n) dm.V[(int64_t)(j + 1) * n + i] = wb[r] / beta;
     // Every block has read scal->stop/amax above; the updates below are seen
-    // only by later kernels on the stream.
+    // only by later kernels on the stream (a block that starts after them
+    // and sees stop set has nothing left to do).
     __syncthreads();
     if (b == 0 && threadIdx.x == 0) {
         scal->k = j + 1;
@@ -603,9 +602,8 @@ hipError_t spectral_bound(const BatchLaunch &B, int steps, uint64_t seed, int fo
     for (int j = 0; j < steps; ++j) {
         symv(SRC_V, j, DST_U, j == 0, false, 1);  // u = X v_j (first step: + column norms)
         symv(SRC_U, j, DST_W, false, true, 1);    // w = X u, pa = V^T w
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 1);
-        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 2);
-        hipLaunchKernelGGL(lz_next_kernel, dim3(nv), dim3(256), 0, s, D, Wv, j, steps);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 1, steps);
+        hipLaunchKernelGGL(lz_orth_kernel, dim3(nv), dim3(kVecThreads), 0, s, D, Wv, j, 2, steps);
     }
     if (steps <= 20)
         hipLaunchKernelGGL(lz_ritz_kernel<20>, dim3(M), dim3(64), 0, s, D);
@@ -743,7 +741,7 @@ hipError_t stage_check(const BatchLaunch &B, int dtype, int sn, int so, int stag
 size_t lanczos_work_doubles(int64_t n, int steps) {
     const int64_t nbv = (n + kRows - 1) / kRows;
     const int64_t tiles = symv_tile_count(n);
-    return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + 4 * tiles * kTB + 64);
+    return (size_t)(n * steps + 5 * n + 2 * nbv * kMaxLanczos + nbv + 4 * tiles * kTB + 64);
 }
 
 int64_t symv_tile_count(int64_t n) {
@@ -769,7 +767,8 @@ void fill_lanczos_desc(MatDesc &d, double *lz, int64_t n, int steps) {
     d.colsq = d.w2 + n;
     d.pa = d.colsq + n;
     d.pb = d.pa + nbv * kMaxLanczos;
-    d.sd = d.pb + nbv * kMaxLanczos;
+    d.pc = d.pb + nbv * kMaxLanczos;
+    d.sd = d.pc + nbv;
     d.sa = d.sd + tiles * kTB;
     d.sd2 = d.sa + tiles * kTB;
     d.sa2 = d.sd2 + tiles * kTB;

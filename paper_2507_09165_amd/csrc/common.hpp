@@ -81,8 +81,9 @@ struct MatDesc {
     int64_t np;       // padded order of the work matrices (GEMM tile multiple)
     int64_t ldw;      // leading dimension of the work matrices (>= np)
     Scalars *scal;
-    // Lanczos work: V (n x steps), vectors (n), partials (nbv x 32), symv tile partials (tiles x 128)
-    double *V, *u, *w, *w2, *colsq, *pa, *pb, *sd, *sa, *sd2, *sa2;
+    // Lanczos work: V (n x steps), vectors (n), partials (nbv x 32, and nbv
+    // for pc), symv tile partials (tiles x 128)
+    double *V, *u, *w, *w2, *colsq, *pa, *pb, *pc, *sd, *sa, *sd2, *sa2;
     void *hi[4], *lo[4];  // work slots: X0, then rotating A / B / X_t
     int32_t nbv;          // vector blocks: ceil(n / 256)
     int32_t fused;        // 1: the whole projection runs in the one-workgroup small-matrix kernel
