@@ -2,9 +2,10 @@
 
 n = 10,000 (the size and launch configuration bench.py times: 256-tile
 rounds, K-split tails, the default FP8-pair split; also FP16 pairs):
-* on the timed GOE input, the oracle itself: its FP64 Lanczos bound (to 1e-9)
-  and its FP64 matrix-product Algorithm 2 with the device's bound, compared in
-  relative Frobenius norm and entry by entry (about a minute of host time);
+* on the timed GOE input and on rank-500 + noise, the oracle itself: its FP64
+  Lanczos bound (to 1e-9) and its FP64 matrix-product Algorithm 2 with the
+  device's bound, compared in relative Frobenius norm and entry by entry
+  (about a minute of host time each);
 * on both inputs, an FP64 eigendecomposition (rocSOLVER dsyevd) of the same
   matrix: the exact projection Q^T diag(max(w, 0)) Q (eq. (3)), held to the
   1e-3 accuracy target, and the FP64 composite polynomial evaluated on the
@@ -35,14 +36,16 @@ def _max_abs_bound(ref, tol):
 
 
 @pytest.mark.timeout(900)
-def test_n10000_timed_input_against_oracle():
+@pytest.mark.parametrize("case", ["goe", "lowrank"])
+def test_n10000_timed_input_against_oracle(case):
     """The bench's timed input and launch configuration (n = 10^4 GOE, seed 4,
-    FP8_FP16_SPLIT) against the oracle itself."""
+    FP8_FP16_SPLIT) and the second n = 10^4 input (rank-500 PSD + noise)
+    against the oracle itself."""
     import torch
     n, mode = 10000, "fp8_fp16_split"
-    X32 = inputs.goe(n, 4)
+    X32 = inputs.goe(n, 4) if case == "goe" else inputs.lowrank_noise(n, 5, 6)
     X = to_dev(X32)
-    say("oracle at full size: device projection")
+    say("oracle at full size: device projection", case)
     out, info_t = P.project_ex(X, mode=mode)
     torch.cuda.synchronize()
     info = P.read_info(info_t)
