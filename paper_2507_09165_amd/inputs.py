@@ -14,6 +14,10 @@ signs):
 * ``clustered``          20% of the eigenvalues in [-1e-3, 1e-3], 80% in [-1, 1].
 * ``dominant``           a few dominant eigenvalues over a dense [-1, 1] spectrum.
 * ``lowrank_noise``      W W^T / n + sqrt(1e-2) (H + H^T) / sqrt(2 n), rank 500.
+* ``householder_spectrum`` eigenvalues uniform in [-1, 1] and a unit vector u:
+                         X = H diag(d) H with H = I - 2 u u^T, dense, with a
+                         known spectrum at any order (the matrix itself is
+                         formed by the caller, e.g. on the device).
 * ``batch_sizes``        256 block sizes, log-uniform in [32, 1024].
 * ``maxcut_graph``       random graphs for the Max-Cut SDPs of the ADMM client.
 """
@@ -46,6 +50,16 @@ def constructed(n: int, seed_q: int, seed_lam: int, lo: float = -1.0, hi: float 
 def from_spectrum(Q: np.ndarray, lam: np.ndarray) -> np.ndarray:
     X = (Q * lam) @ Q.T
     return (0.5 * (X + X.T)).astype(np.float32)
+
+
+def householder_spectrum(n: int, seed: int, lo: float = -1.0, hi: float = 1.0):
+    """(d, u), FP64: eigenvalues d uniform in [lo, hi] and a unit vector u;
+    X = H diag(d) H with the reflector H = I - 2 u u^T has the eigenvalues d
+    and eigenvectors the columns of H."""
+    rng = _rng(seed)
+    d = rng.uniform(lo, hi, size=n)
+    u = rng.standard_normal(n)
+    return d, u / np.linalg.norm(u)
 
 
 def dominant(n: int, seed: int, top=(1000.0,)):

@@ -12,6 +12,11 @@ rounds, K-split tails, the default FP8-pair split; also FP16 pairs):
   spectrum, Q^T diag(lam g(w / lam)) Q with the oracle's scalar filter g and
   the device's bound lam (a polynomial of a symmetric matrix acts on its
   eigenvalues), held to the polynomial tolerance.
+n = 32768 (the largest order tested: work matrices past 2^31 bytes, 32 whole
+rounds of 256 tiles plus a 64-tile tail in 4 K-chunks): a dense matrix with a
+known spectrum, X = H diag(d) H with a Householder reflector H, against the
+closed forms H diag(lam g(d / lam)) H (the FP64 composite polynomial on the
+spectrum, device bound) and H diag(max(d, 0)) H (eq. (3)), entry for entry.
 n = 5782 (the first size band of whole 256-tile rounds plus an 8-chunk K-split
 tail, default tuning) and n = 4096 (FP16 and BF16 on the GOE and clustered
 spectra): the oracle's FP64 matrix-product form.
@@ -123,6 +128,68 @@ def test_n10000_launch_configuration(case):
         assert e_poly <= TOL_POLY[mode]
         assert e_ex <= 1e-3
         del out, poly, o
+
+
+def _householder_dense(d, u):
+    """H diag(d) H = diag(d) - 2 (u (d u)^T + (d u) u^T) + 4 (u^T D u) u u^T,
+    FP64 on the device (exactly symmetric: each entry's two products are
+    summed in the same order as its mirror's)."""
+    import torch
+    du = u * d
+    M = torch.outer(u, du)
+    M += torch.outer(du, u)
+    M *= -2.0
+    M += (4.0 * float(torch.dot(u, du))) * torch.outer(u, u)
+    M.diagonal().add_(d)
+    return M
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["fp8_fp16_split", "fp16"])
+def test_n32768_householder_spectrum(mode):
+    """The largest order tested, n = 32768 (3.3x the headline order), on a
+    dense matrix with a known spectrum (eigenvalues uniform in [-1, 1]): the
+    bound sits at the spectral radius, and the result matches the FP64
+    composite polynomial on the spectrum with the device's bound (relative
+    Frobenius norm and entry by entry) and, in the split default, the exact
+    projection to the 1e-3 target."""
+    import torch
+    n = 32768
+    say("largest order", mode, n)
+    d64, u64 = inputs.householder_spectrum(n, 31)
+    d = torch.from_numpy(d64).to("cuda")
+    u = torch.from_numpy(u64).to("cuda")
+    X = _householder_dense(d, u).float()
+    torch.cuda.synchronize()
+    say("  input formed")
+    out, info_t = P.project_ex(X, mode=mode)
+    torch.cuda.synchronize()
+    info = P.read_info(info_t)
+    lam = info["lambda"]
+    del X
+    rho = float(torch.max(torch.abs(d)))
+    say(f"  lam {lam:.6f} rho {rho:.6f}")
+    assert info["nonfinite"] == 0 and info["fallback"] == 0
+    assert 0.999 * rho <= lam <= 1.01 * rho
+    assert torch.equal(out, out.t())
+    o = out.double()
+    del out
+    h = torch.from_numpy(lam * oracle.g_scalar(d64 / lam, mode)).to("cuda")
+    ref = _householder_dense(h, u)
+    e_poly = _torch_rel(o, ref)
+    emax = float(torch.max(torch.abs(o - ref)))
+    # entries against the reference's spectral norm (max |h|), which bounds
+    # every entry of it: the diagonal carries O(1) entries, the rest O(1 / n)
+    bound = TOL_POLY[mode] * float(torch.max(torch.abs(h)))
+    del ref
+    exact = _householder_dense(torch.clamp(d, min=0.0), u)
+    e_ex = _torch_rel(o, exact)
+    del exact, o
+    say(f"  vs poly {e_poly:.3e} (max abs {emax:.3e}, bound {bound:.3e}) vs exact {e_ex:.3e}")
+    assert e_poly <= TOL_POLY[mode]
+    assert emax <= bound
+    if mode == "fp8_fp16_split":
+        assert e_ex <= 1e-3
 
 
 @pytest.mark.parametrize("case", ["goe", "clustered"])
