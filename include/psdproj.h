@@ -94,18 +94,28 @@ typedef enum {
 
 /* split_mask flag: split only the B product of the masked stages */
 #define PSDPROJ_SPLIT_B_ONLY 0x40000000u
+/* split_mask bits PSDPROJ_SPLIT_B_SHIFT + t (t < 14): stage t+1 splits only its
+ * B product (a stage also set in bits 0..15 splits in full) */
+#define PSDPROJ_SPLIT_B_SHIFT 16
 
 typedef struct {
     int mode;                 /* psdproj_mode */
     int lanczos_steps;        /* 0 -> 20 (Section 3.4); at most 32 */
     uint32_t split_mask;      /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: bit t set ->
                                  stage t+1 uses split products; 0 -> the mode's
-                                 default (stages 2-3; BF16: 1-4). Bit 31 set:
+                                 default (FP16_SPLIT: stages 2-3; FP8_FP16_SPLIT:
+                                 stage 3, and stages 1-2 B-only; the BF16 forms:
+                                 1-4). Bit 31 set:
                                  bits 0..29 are taken as given even when all zero
                                  (e.g. 0x80000000 = no split stage). Bit 30
                                  (PSDPROJ_SPLIT_B_ONLY): in the masked stages only
                                  B = b A + c A^2 is split; A = X X stays plain and
-                                 X' = a X + B X has one split operand */
+                                 X' = a X + B X has one split operand. Without
+                                 bit 30, bits 16..29 name such B-only stages
+                                 beside the fully split ones of bits 0..15
+                                 (PSDPROJ_SPLIT_B_SHIFT). Matrices of the
+                                 one-workgroup path (order <= the "small_max"
+                                 tuning key) split B-only stages in full */
     int split_final;          /* BF16, FP16_SPLIT, FP8_FP16_SPLIT: -1 default (0),
                                  0 plain, 1 split final product */
     double lambda_override;   /* > 0: use this bound instead of the Lanczos bound */

@@ -59,6 +59,19 @@ constexpr uint32_t kExplicitMask = 0x80000000u;
 // pair; A = X X stays plain and X' = a X + B X is a one-sided split product
 // (split operand B on the left, since B and X commute).
 constexpr uint32_t kSplitBOnly = PSDPROJ_SPLIT_B_ONLY;
+// split_mask bits 16..29: bit 16 + t makes stage t + 1 such a B-only stage
+// (a stage also set in bits 0..15 is split in full).
+constexpr int kBOnlyShift = PSDPROJ_SPLIT_B_SHIFT;
+// FP8_FP16_SPLIT default: stage 3 split in full and stages 1-2 B-only (26
+// product-equivalents instead of 28 for stages 2-3 in full). The stages'
+// contributions to the squared error add up nearly independently (stages
+// 2-3 predicted from the single-stage splits within 0.1%), and a B-only stage
+// removes about 60% of its stage's share at a quarter of the full split's
+// cost. Measured at n = 10^4 against an FP64 eigen-projection: 8.3e-4 (GOE)
+// and 4.7e-4 (rank-500 + noise), 30.0 ms, against 7.4e-4 / 4.8e-4 and 31.9
+// ms for stages 2-3 in full; single full stages miss 1e-3 on GOE (1.10e-3 at
+// best). Matrices of the one-workgroup path split these stages in full.
+constexpr uint32_t kDefaultSplitMaskFp8 = 0x4u | (0x3u << kBOnlyShift);
 
 struct StagePlan {
     int T = 0;
@@ -71,7 +84,7 @@ struct StagePlan {
     int dtype = DT_F32;
     uint32_t split_mask = 0;
     bool split_final = false;
-    bool b_only = false;  // kSplitBOnly: only B is split in the masked stages
+    uint32_t b_mask = 0;  // stages in which only B is split (disjoint from split_mask)
     // FP8-pair code exponents (DT_F16X8): X_t (t = 0..T), A and B of stage t
     int ex[17], ea[16], eb[16];
 };
@@ -167,11 +180,18 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
     if (o.mode == PSDPROJ_MODE_FP16_SPLIT || o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT || o.mode == PSDPROJ_MODE_BF16 ||
         o.mode == PSDPROJ_MODE_FP8_BF16_SPLIT) {
         const bool bf = o.mode == PSDPROJ_MODE_BF16 || o.mode == PSDPROJ_MODE_FP8_BF16_SPLIT;
-        const uint32_t def = bf ? kDefaultSplitMaskBf16 : kDefaultSplitMask;
+        const uint32_t def = bf ? kDefaultSplitMaskBf16
+                                : o.mode == PSDPROJ_MODE_FP8_FP16_SPLIT ? kDefaultSplitMaskFp8 : kDefaultSplitMask;
         const uint32_t m = (o.split_mask & kExplicitMask) ? (o.split_mask & ~kExplicitMask)
                                                           : (o.split_mask ? o.split_mask : def);
-        p.split_mask = m & ((1u << T) - 1);
-        p.b_only = (m & kSplitBOnly) != 0 && p.split_mask != 0;
+        const uint32_t stages = (1u << T) - 1;
+        if (m & kSplitBOnly) {  // every masked stage B-only
+            p.b_mask = m & stages & 0xFFFFu;
+            p.split_mask = 0;
+        } else {
+            p.split_mask = m & stages & 0xFFFFu;
+            p.b_mask = (m >> kBOnlyShift) & 0x3FFFu & stages & ~p.split_mask;
+        }
         p.split_final = o.split_final < 0 ? kDefaultSplitFinal : o.split_final != 0;
     } else if (o.mode == PSDPROJ_MODE_FP32_EMU) {
         // every product on hi + lo FP16 pairs: ~22-bit operands, FP32 accumulation
@@ -182,6 +202,9 @@ bool make_stage_plan(const psdproj_opts &o, StagePlan &p) {
     return true;
 }
 
+// Whether any work matrix of the plan is stored split (lo slots needed).
+bool any_split(const StagePlan &p) { return p.split_mask != 0 || p.b_mask != 0 || p.split_final; }
+
 size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 
 // Orders up to this value run the whole projection in the one-workgroup
@@ -189,12 +212,13 @@ size_t elt_size(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 static std::atomic<int> g_small_max{kSmallEdge};
 
 // Whether matrix n of a plan runs in the one-workgroup kernel: half-precision
-// work formats with whole-stage splits, no adaptive depth, no deflation. The
+// work formats (B-only stages split in full there), no adaptive depth, no
+// deflation. The
 // rule depends only on (n, mode, options), so a matrix takes the same path
 // alone and in any batch.
 bool plan_fused(int64_t n, const StagePlan &p, int deflate, int small_max) {
     const bool half = p.dtype == DT_F16 || p.dtype == DT_BF16 || p.dtype == DT_F16X8 || p.dtype == DT_BF16X8;
-    return n >= 1 && n <= small_max && half && !p.cubic && !p.adaptive && !p.b_only && deflate == 0 && p.T <= 16;
+    return n >= 1 && n <= small_max && half && !p.cubic && !p.adaptive && deflate == 0 && p.T <= 16;
 }
 
 // Products of this matrix run on 256 tiles: plain ones whenever the size
@@ -228,7 +252,7 @@ MatLayout mat_layout(int64_t n, const StagePlan &p, int steps, int64_t defl_ld) 
     L.n = n;
     L.np = gemm_padded_size(n, plan_big(n, p));
     L.ldw = (L.np >= 2048 && L.np % 1024 == 0) ? L.np + g_ld_pad : L.np;
-    const bool split = p.split_mask != 0 || p.split_final;
+    const bool split = any_split(p);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
     L.off_scal = take(sizeof(Scalars));
@@ -256,7 +280,7 @@ struct Plan {
     bool adaptive = false;
     int64_t defl_ld = 0;   // caller's leading dimension when deflating
     uint32_t split_mask = 0;
-    bool b_only = false;
+    uint32_t b_mask = 0;
     int small_max = 0;     // the small-matrix rule the plan was laid out for
     std::vector<int64_t> ns;
     // layout
@@ -308,7 +332,7 @@ struct Plan {
                   int64_t dld) const {
         return mode == o.mode && steps == st && split_mask == rq.split_mask && split_final == (int)rq.split_final &&
                ns == n && tile_gen == gemm_tile_generation() && deflate == o.deflate && defl_ld == dld &&
-               stages == rq.T && adaptive == rq.adaptive && b_only == rq.b_only && small_max == g_small_max.load();
+               stages == rq.T && adaptive == rq.adaptive && b_mask == rq.b_mask && small_max == g_small_max.load();
     }
 };
 
@@ -375,7 +399,7 @@ int build_tables(Plan &P, void *base, hipStream_t s) {
     std::vector<MatDesc> desc(M);
     std::vector<WorkItem> wv, wt, wc, wf;
     std::vector<std::pair<DeflState *, DeflState>> defl_init;
-    const bool split = P.sp.split_mask != 0 || P.sp.split_final;
+    const bool split = any_split(P.sp);
     for (size_t m = 0; m < M; ++m) {
         const MatLayout &L = P.mats[m];
         uint8_t *mb = b + P.mat_off[m];
@@ -674,7 +698,7 @@ int run_plan(Plan &P, const IoArg *ios, const psdproj_opts &o, hipStream_t s, bo
         a.io0 = B.io0;
         a.T = p.T;
         a.steps = P.steps;
-        a.split_mask = p.split_mask;
+        a.split_mask = p.split_mask | p.b_mask;  // B-only stages split in full here
         a.split_final = p.split_final ? 1 : 0;
         a.bound_only = bound_only ? 1 : 0;
         a.force_fallback = o.force_bound_fallback;
@@ -734,7 +758,7 @@ int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s
     hipError_t e = spectral_bound(B, P.steps, kLanczosSeed, o.force_bound_fallback, o.lambda_override, s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
     if (bound_only) return PSDPROJ_OK;
-    const bool x0_split = p.split_final || ((p.split_mask & 1u) && !p.b_only);
+    const bool x0_split = p.split_final || (p.split_mask & 1u);
     e = cast_x0(B, p.dtype, x0_split, p.ex[0], s);
     if (e != hipSuccess) return PSDPROJ_ERR_HIP;
 
@@ -784,7 +808,7 @@ int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s
     };
     // slot 0 holds X0; slots 1..3 rotate: A -> pa, B -> pb, X' -> pa
     int cur = 0;
-    bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
+    bool cur_split = (p.split_mask & 1u) != 0;
     double *adapt_part = (double *)(b + P.off_adapt);
     // unsplit FP8-pair storage is FP16 / BF16
     const int check_dt = p.dtype == DT_F16X8 ? DT_F16 : p.dtype == DT_BF16X8 ? DT_BF16 : p.dtype;
@@ -798,9 +822,10 @@ int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s
     for (int t = 0; t < p.T; ++t) {
         g.adaptive = (p.adaptive && t >= p.adapt_from) ? 1 : 0;
         const bool sp = (p.split_mask >> t) & 1u;
-        // whether X' is stored split (B-only plans: only for a split final product)
-        const bool next_split = p.b_only ? (t + 1 == p.T && p.split_final)
-                                         : (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
+        const bool bo = (p.b_mask >> t) & 1u;
+        // whether X' is stored split: when the next stage splits in full or
+        // the final product is split (a B-only stage reads X plain)
+        const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         int pa = -1, pb = -1;
         for (int k = 1; k < 4; ++k)
             if (k != cur) { if (pa < 0) pa = k; else if (pb < 0) pb = k; }
@@ -814,15 +839,16 @@ int run_sequence_of(Plan &P, BatchLaunch B, const psdproj_opts &o, hipStream_t s
             cur = pb;
             continue;
         }
-        if (p.b_only && sp) {
+        if (bo) {
             // A = X X; B = b A + c A A, stored as a pair; X' = a X + B X with
-            // only B split (X is never split before the final product here)
+            // only B split among the operands (X enters with its hi part; the
+            // addend a X takes its pair when X is stored split)
             e = product(cur, false, cur, false, -1, false, 0.f, 1.f, 0.f, pa, EPI_STORE, p.ea[t]);
             if (e != hipSuccess) return PSDPROJ_ERR_HIP;
             e = product(pa, false, pa, false, pa, false, (float)p.b[t], (float)p.c[t], 0.f, pb, EPI_STORE_SPLIT,
                         p.eb[t]);
             if (e != hipSuccess) return PSDPROJ_ERR_HIP;
-            e = product(pb, true, cur, false, cur, false, (float)p.a[t], 1.f, 0.f, pa,
+            e = product(pb, true, cur, false, cur, cur_split, (float)p.a[t], 1.f, 0.f, pa,
                         next_split ? EPI_STORE_SPLIT : EPI_STORE, p.ex[t + 1]);
             if (e != hipSuccess || check(t, pa, cur) != hipSuccess) return PSDPROJ_ERR_HIP;
             cur = pa;
@@ -876,7 +902,7 @@ std::unique_ptr<Plan> new_plan(const psdproj_opts &o, const StagePlan &sp, int s
     P->sp = sp;
     P->split_mask = sp.split_mask;
     P->split_final = sp.split_final;
-    P->b_only = sp.b_only;
+    P->b_mask = sp.b_mask;
     P->small_max = g_small_max.load();
     P->ns = ns;
     P->tile_gen = gemm_tile_generation();
@@ -995,7 +1021,7 @@ int run_projection(const psdproj_opts &o, int64_t n, int64_t ld, const float *X,
     if (!X || (!out && !bound_only)) return PSDPROJ_ERR_INVALID_ARG;
     if (n > (int64_t)1 << 20) return PSDPROJ_ERR_UNSUPPORTED;
     if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
-    if (tmp.adaptive && (tmp.split_mask || tmp.split_final)) return PSDPROJ_ERR_UNSUPPORTED;
+    if (tmp.adaptive && any_split(tmp)) return PSDPROJ_ERR_UNSUPPORTED;
     psdproj_opts oo = o;
     if (bound_only) oo.deflate = 0;
     const int64_t defl_ld = oo.deflate > 0 ? ld : 0;
@@ -1026,7 +1052,7 @@ int run_batched(const psdproj_opts &o, int count, const int64_t *n, const int64_
     }
     if (o.deflate < 0 || o.deflate > kMaxDeflate) return PSDPROJ_ERR_INVALID_ARG;
     if (o.deflate > 0) return PSDPROJ_ERR_UNSUPPORTED;  // deflation: single projections only
-    if (tmp.adaptive && (tmp.split_mask || tmp.split_final)) return PSDPROJ_ERR_UNSUPPORTED;
+    if (tmp.adaptive && any_split(tmp)) return PSDPROJ_ERR_UNSUPPORTED;
     if (ns.empty()) return PSDPROJ_OK;
     const int steps = o.lanczos_steps ? o.lanczos_steps : kDefaultLanczos;
     if (steps < 1 || steps > kMaxLanczos) return PSDPROJ_ERR_INVALID_ARG;
@@ -1179,22 +1205,21 @@ double gemm_count_for(const psdproj_opts &o) {
     const double pair = x8 ? 2.0 : 3.0;
     const double one = x8 ? 1.5 : 2.0;
     double g = 0;
-    bool cur_split = (p.split_mask & 1u) != 0 && !p.b_only;
+    bool cur_split = (p.split_mask & 1u) != 0;
     for (int t = 0; t < p.T; ++t) {
         const bool sp = (p.split_mask >> t) & 1u;
-        if (p.b_only) {
-            g += sp ? 2.0 + one : 3.0;  // X X and A A plain; B X one-sided in split stages
-            continue;
-        }
         const bool next_split = (t + 1 < p.T) ? ((p.split_mask >> (t + 1)) & 1u) : p.split_final;
         const bool xs = sp && cur_split;
-        g += xs ? pair : 1;               // X X
-        g += sp ? pair : 1;               // A A
-        g += sp ? (xs ? pair : one) : 1;  // X B
+        if ((p.b_mask >> t) & 1u) {
+            g += 2.0 + one;  // X X and A A plain, B X one-sided
+        } else {
+            g += xs ? pair : 1;               // X X
+            g += sp ? pair : 1;               // A A
+            g += sp ? (xs ? pair : one) : 1;  // X B
+        }
         cur_split = next_split;
     }
-    // a split final product multiplies X0 and X_T both split (B-only plans:
-    // X0 split, X_T split by the last stage)
+    // a split final product multiplies X0 and X_T, both stored split
     g += p.split_final ? pair : 1;
     return g;
 }

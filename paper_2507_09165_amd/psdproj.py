@@ -137,6 +137,8 @@ def _check_matrix(X, name="X"):
 EXPLICIT_MASK = 0x80000000
 # split_mask flag: in the masked stages only B = b A + c A^2 is split
 SPLIT_B_ONLY = 0x40000000
+# split_mask bits SPLIT_B_SHIFT + t: stage t + 1 splits only its B product
+SPLIT_B_SHIFT = 16
 
 
 def make_opts(mode="fp16", lanczos_steps=0, split_mask=None, split_final=-1, lambda_override=0.0,

@@ -356,6 +356,34 @@ def test_ksplit_tail_tiles(mode):
     assert rel_fro(out, ref_t.cpu().numpy()) <= 2 * TOL_POLY[mode]  # both within TOL of the oracle
 
 
+@pytest.mark.parametrize("mode", ["fp8_fp16_split", "fp16_split"])
+def test_per_stage_b_only_masks(mode):
+    """B-only stages named per stage (split_mask bits 16 + t) beside fully
+    split ones: the FP8_FP16_SPLIT default is stage 3 in full and stages 1-2
+    B-only (bitwise the explicit mask); a stage in both masks splits in full
+    (bitwise the plain full mask); every mix, B-only stages alone and a
+    B-only stage before and after a full one, within the oracle tolerance."""
+    X32 = inputs.goe(777, 41)
+    X = X32.astype(np.float64)
+    sh = P.SPLIT_B_SHIFT
+    say("per-stage b-only", mode)
+    if mode == "fp8_fp16_split":
+        d, _ = _run(X32, mode)
+        e, _ = _run(X32, mode, split_mask=0x4 | (0x3 << sh))
+        np.testing.assert_array_equal(d, e)
+    both, _ = _run(X32, mode, split_mask=0x6 | (0x6 << sh))
+    full, _ = _run(X32, mode, split_mask=0x6)
+    np.testing.assert_array_equal(both, full)
+    for mask in (0x4 | (0x3 << sh), 0x4 | (0xB << sh), 0x2 | (0xC << sh), 0x3 << sh, 0x1 | (0x2 << sh)):
+        for final in (0, 1):
+            out, info = _run(X32, mode, split_mask=mask, split_final=final)
+            ref, _ = oracle.project_poly(X, mode, lam=info["lambda"])
+            err = rel_fro(out, ref)
+            say(f"   mask {mask:#x} final {final}: {err:.3e}")
+            np.testing.assert_array_equal(out, out.T)
+            assert err <= TOL_POLY[mode], (mask, final, err)
+
+
 @pytest.mark.parametrize("mode", ["bf16", "fp8_bf16_split"])
 def test_b_only_split_stages_bf16(mode):
     """The B-only split on a BF16 bulk (one-sided BF16 pair products, or FP8

@@ -56,6 +56,13 @@ def test_gemm_counts():
     # a split product: 3 FP16 products with FP16 lo halves, 2 with FP8 pairs
     assert P.gemm_count("fp16_split", split_mask=0x6, split_final=0) == 22 + 6 * 2
     assert P.gemm_count("fp8_fp16_split", split_mask=0x6, split_final=0) == 22 + 6
+    # default: stage 3 in full (2 extra), stages 1-2 B-only (0.5 extra each)
+    sh = P.SPLIT_B_SHIFT
+    assert P.gemm_count("fp8_fp16_split") == P.gemm_count("fp8_fp16_split", split_mask=0x4 | (0x3 << sh)) == 26
+    assert P.gemm_count("fp8_fp16_split", split_mask=0x4 | (0xB << sh)) == 22 + 3 + 3 * 0.5
+    # a stage set in both masks splits in full
+    assert P.gemm_count("fp8_fp16_split", split_mask=0x6 | (0x6 << sh)) == 28
+    assert P.gemm_count("fp16_split", split_mask=0x4 | (0x3 << sh)) == 22 + 6 + 2 * 1
     assert P.gemm_count("fp8_fp16_split", split_mask=0x7F, split_final=1) == 44
     # B-only split stages: X X and A A plain, B X one-sided (2 FP16 products
     # with FP16 lo halves, 1.5 with FP8 pairs)
