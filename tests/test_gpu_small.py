@@ -105,6 +105,22 @@ def test_mixed_batch_equals_single(mode):
         assert infos[i]["lambda"] == P.read_info(alone[i][1])["lambda"], n
 
 
+@pytest.mark.parametrize("mode", ["fp8_fp16_split", "fp16_split"])
+def test_small_b_only_stages_split_in_full(mode):
+    """The one-workgroup path has no one-sided product: a stage named B-only
+    (split_mask bits 16 + t) is split in full there, so the mixed mask gives
+    the bits of the full mask over the same stages, and the result meets the
+    oracle."""
+    sh = P.SPLIT_B_SHIFT
+    for n in (40, 128):
+        X32 = _matrix(n, 700 + n)
+        mixed, info = _run(X32, mode, split_mask=0x4 | (0x3 << sh))
+        full, _ = _run(X32, mode, split_mask=0x7)
+        np.testing.assert_array_equal(mixed, full)
+        ref, _ = oracle.project_poly(X32.astype(np.float64), mode, lam=info["lambda"])
+        assert rel_fro(mixed, ref) <= TOL_POLY
+
+
 def test_small_degenerate_inputs():
     import torch
     n = 50
